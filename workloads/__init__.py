@@ -1,0 +1,124 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module only draws random numbers and shapes them into the input fields of
+the workloads (right-hand sides, wavenumber fields, the Gaussian test blocks of
+the randomised SVD).  It holds none of the solver's arithmetic: no operator, no
+decomposition rule, no solve.  Sizes that depend on the decomposition (the
+interface dimension of a subdomain, its sketch width) are passed in by the
+caller.
+
+Every generator takes an explicit integer seed and uses NumPy's PCG64, so the
+same call gives the same array on any machine.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "complex_gaussian",
+    "box_filter5",
+    "smoothed_gaussian_rhs",
+    "white_rhs",
+    "gaussian_random_field",
+    "wavenumber_grf",
+    "omega_block",
+    "WORKLOADS",
+]
+
+
+def _rng(*key: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(list(int(k) for k in key)))
+
+
+def complex_gaussian(shape, seed: int, *stream: int) -> np.ndarray:
+    """Standard complex Gaussian CN(0,1): real and imaginary parts i.i.d. N(0, 1/2)."""
+    g = _rng(seed, *stream)
+    re = g.standard_normal(shape)
+    im = g.standard_normal(shape)
+    return (re + 1j * im) / np.sqrt(2.0)
+
+
+def box_filter5(w: np.ndarray) -> np.ndarray:
+    """5x5 moving mean with zero padding, same output size, divided by 25."""
+    n0, n1 = w.shape
+    pad = np.zeros((n0 + 4, n1 + 4), dtype=w.dtype)
+    pad[2:-2, 2:-2] = w
+    out = np.zeros_like(w)
+    for a in range(5):
+        for b in range(5):
+            out += pad[a:a + n0, b:b + n1]
+    return out / 25.0
+
+
+def white_rhs(n_nodes: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    """nrhs i.i.d. CN(0,1) vectors of length n_nodes, shape (nrhs, n_nodes)."""
+    return complex_gaussian((nrhs, n_nodes), seed, 1)
+
+
+def smoothed_gaussian_rhs(n_cells: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    """CN(0,1) on the (N+1)^2 node grid, smoothed by the 5x5 box filter.
+
+    Returns shape (nrhs, (N+1)^2), node (p, q) at p*(N+1)+q.
+    """
+    n = n_cells + 1
+    out = np.empty((nrhs, n * n), dtype=np.complex128)
+    for j in range(nrhs):
+        w = complex_gaussian((n, n), seed, 2, j)
+        out[j] = box_filter5(w).reshape(-1)
+    return out
+
+
+def gaussian_random_field(n_cells: int, corr_len: float, seed: int) -> np.ndarray:
+    """Zero-mean, unit-variance stationary field on the (N+1)^2 nodes.
+
+    Covariance exp(-|x-y|^2 / (2 l^2)), sampled by circulant embedding on a
+    periodic grid of 2(N+1) points per side (spectral square root of the
+    embedded covariance, negative eigenvalues clipped to zero), then rescaled to
+    unit sample variance.
+    """
+    n = n_cells + 1
+    h = 1.0 / n_cells
+    m = 2 * n
+    d = np.minimum(np.arange(m), m - np.arange(m)) * h
+    cov = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2.0 * corr_len ** 2))
+    lam = np.fft.fft2(cov).real
+    lam = np.maximum(lam, 0.0)
+    g = _rng(seed, 3)
+    z = g.standard_normal((m, m)) + 1j * g.standard_normal((m, m))
+    field = np.fft.fft2(np.sqrt(lam / (m * m)) * z).real[:n, :n]
+    field = field - field.mean()
+    field = field / field.std()
+    return field.reshape(-1)
+
+
+def wavenumber_grf(n_cells: int, k0: float, amp: float, corr_len: float, seed: int) -> np.ndarray:
+    """k(x) = k0 (1 + amp * clip(s(x), -1, 1)) on the nodes, s a unit Gaussian field."""
+    s = gaussian_random_field(n_cells, corr_len, seed)
+    return k0 * (1.0 + amp * np.clip(s, -1.0, 1.0))
+
+
+def omega_block(seed: int, level: int, box: int, m_in: int, s: int) -> np.ndarray:
+    """Gaussian test block of the randomised SVD for one subdomain.
+
+    Shape (s, m_in): row t is the t-th sample vector on the subdomain's
+    interface nodes (entries CN(0,1)).  Seeded per (seed, level, box).
+    """
+    return complex_gaussian((s, m_in), seed, 4, level, box)
+
+
+# Workload definitions (sizes and seeds of the synthetic problems).
+WORKLOADS = {
+    # 1D, k = 20*pi, 2000 interior + 2 boundary nodes, two subdomains
+    # overlapping by 20 cells, one interface mode per subdomain.
+    "helm1d_n2001_k20pi": dict(dim=1, n_cells=2001, k=20.0 * np.pi, m=[(2, 1)],
+                               overlap=[20], rank=1, oversample=10, rhs="white"),
+    # 2D free space, 256 cells per side, k = 40, 4x4 subdomains, 4-cell overlap,
+    # rank 8 per interface + 10 oversampling, smoothed Gaussian RHS.
+    "helm2d_n256_k40_4x4": dict(dim=2, n_cells=256, k=40.0, m=[(4, 4)], overlap=[4],
+                                rank=8, oversample=10, rhs="smooth"),
+    # 2D hierarchical, 1024 cells per side, heterogeneous k, [2x2, 2x2, 2x2].
+    "helm2d_n1024_grf_3lvl": dict(dim=2, n_cells=1024, k=160.0, k_amp=0.3, k_corr=0.1,
+                                  m=[(2, 2), (2, 2), (2, 2)], overlap=[8, 8, 8],
+                                  rank=16, oversample=10, rhs="smooth"),
+}
