@@ -1,0 +1,157 @@
+/*
+ * helmdd.h - C ABI of the hierarchical ORAS solver with randomised-SVD coarse
+ * spaces for the impedance Helmholtz problem (MI355X / gfx950).
+ *
+ * Method (Gander, Jiang, Zhang, "Hierarchical Coarse Basis by Randomised SVD:
+ * the Helmholtz Problem"):
+ *   - problem: -u'' - k^2 u = f with impedance conditions d_n u - i k u = g
+ *     (eq. (lap1), Sec. 1; in 2D the free-space problem of Sec. 3.1), here
+ *     discretised by the cell-assembled 5-point (1D: 3-point) scheme on
+ *     (N+1)^dim nodes, h = 1/N;
+ *   - one step: ORAS smoothing u~ = u + sum_i P_i A~_i^{-1} R_i (f - A u)
+ *     (eq. (sub1), Richardson form) followed by the coarse correction
+ *     u = u~ + C A_c^{-1} C^H (f - A u~), A_c = C^H A C (eq. (coarse1));
+ *   - coarse basis C = (C_i), C_i = P_i A~_i^{-1} B_i^T V_i with V_i the
+ *     dominant right singular vectors of the interface map
+ *     T_i = B_i^o A~_i^{-1} B_i^T, found by a randomised SVD (Sec. 2);
+ *   - hierarchy: each subdomain problem is itself solved by n_i steps of the
+ *     same two-level method on its children (Sec. 1, Sec. 2, Sec. 3 notation
+ *     [m_x1 x m_y1, ...], n_c, n_i).
+ *
+ * Conventions
+ *   - Every call returns hh_status; nothing throws across the boundary.
+ *   - Complex numbers are interleaved (re, im) doubles ("c128").
+ *   - Node (p, q), 0 <= p, q <= N, has index p*(N+1) + q (1D: index p).
+ *   - Device pointers are HIP device memory owned by the caller; the library
+ *     never frees them.  The context owns every internal allocation
+ *     (factorisations, coarse bases, A_c^{-1}, work space) until hh_destroy.
+ *   - All device work is enqueued on hh_options.stream (null: the default
+ *     stream).  Calls return after the work they started has completed,
+ *     except where stated.  A context is used by one host thread at a time.
+ *   - On HH_EDEVICE the context is poisoned: only hh_destroy is valid.
+ */
+#ifndef HELMDD_H
+#define HELMDD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HH_OK = 0,
+  HH_EINVAL = 1,       /* invalid argument or shape; no side effect */
+  HH_ENOMEM = 2,       /* device allocation failed; context unchanged */
+  HH_EDEVICE = 3,      /* HIP error; context poisoned */
+  HH_ENOTCONV = 4,     /* outer loop hit maxit; u holds the last iterate */
+  HH_ESINGULAR = 5,    /* zero pivot in a leaf factorisation or in A_c */
+  HH_ESTATE = 6,       /* call out of order (e.g. solve before the coarse build) */
+  HH_EUNSUPPORTED = 7  /* valid but not implemented (size limits below) */
+} hh_status;
+
+typedef enum { HH_FP64 = 0, HH_MIXED = 1 } hh_precision;
+typedef enum { HH_STATIONARY = 0, HH_GMRES = 1 } hh_outer;
+
+typedef struct hh_ctx hh_ctx; /* opaque */
+
+/* The operator of eq. (lap1) / Sec. 3.1: dim 1 or 2, N cells per side,
+ * wavenumber per node (host array of (N+1)^dim doubles, copied by hh_setup)
+ * or the constant k_const when k is null. */
+typedef struct {
+  int32_t dim;
+  int32_t n_cells;
+  const double* k;
+  double k_const;
+} hh_operator;
+
+/* The decomposition [m_x1 x m_y1, ..., m_xl x m_yl] of Sec. 3: level l splits
+ * every box of level l-1 into m[l-1][0] x m[l-1][1] boxes (1D: m[l-1][1] is
+ * ignored).  overlap_cells[l-1] = delta/h (even): each box is extended by
+ * delta/(2h) cells on every side interior to its parent.  inner_iters[l-1] =
+ * n_i, the number of two-level steps that solve a level-l box problem when
+ * the box has children (default 1 when 0). */
+typedef struct {
+  int32_t levels;
+  int32_t m[8][2];
+  int32_t overlap_cells[8];
+  int32_t inner_iters[8];
+} hh_decomposition;
+
+typedef struct {
+  int32_t precision;     /* hh_precision: HH_MIXED keeps the leaf factors in complex64 */
+  int32_t outer;         /* hh_outer used by hh_solve */
+  int32_t gmres_restart; /* restart length (default 50 when <= 0) */
+  void* stream;          /* hipStream_t, or null */
+} hh_options;
+
+typedef struct {
+  int32_t iters;        /* preconditioner applications */
+  int32_t converged;    /* 1 if ||f - A u|| / ||f|| < rtol */
+  double rel_residual;  /* true relative residual at exit */
+} hh_solve_info;
+
+/* Builds the decomposition, uploads k and factorises every leaf box problem
+ * A~_i (local impedance conditions, eq. (sub1)) on the device.  Leaf boxes must
+ * have at most 256 nodes along q.  HH_ESINGULAR if a leaf factorisation meets a
+ * zero pivot. */
+hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_options* o, hh_ctx** out);
+
+/* Number of boxes of a level (0 = the whole domain) and, per box, its interface
+ * size m_in, coarse rank r_i = min(rank_per_interface * n_if, m_in) and sketch
+ * width s_i = min(r_i + oversample, m_in) (n_if = interface sides of the box).
+ * Arrays have n_boxes entries; any of them may be null. */
+hh_status hh_level_info(const hh_ctx* c, int32_t level, int32_t rank_per_interface, int32_t oversample,
+                        int32_t* n_boxes, int32_t* m_in, int32_t* r, int32_t* s);
+
+/* Randomised SVD of every interface map of `level` and the coarse spaces of
+ * the parents at level-1 (Sec. 2): Y = T_i Omega_i, Q = qr(Y),
+ * B^H = T_i^* Q, V_i = top-r_i right singular vectors of B,
+ * C_i = P_i S_i(B_i^T V_i), A_c = C^H A C and A_c^{-1} (FP64, partial pivoting).
+ * Must be called for level L, L-1, ..., 1 in this order (an upper level's
+ * sub-solves use the coarse spaces below it), else HH_ESTATE.
+ * omega: device c128, the Gaussian blocks of the level's boxes concatenated in
+ * box order, block i column-major m_in x s_i (sample t = column t); null is
+ * valid only when rank_per_interface == 0 (no coarse space at this level). */
+hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank_per_interface, int32_t oversample,
+                          const void* omega);
+
+/* Solves A u = b for nrhs right-hand sides: b = f + impedance data g (2D:
+ * (boundary edges at the node)/2 * g/h, 1D: g/h at the end nodes).
+ * f, g, u: device c128 arrays [nrhs][(N+1)^dim]; g may be null (g = 0).
+ * u0 = 0; the outer loop (hh_options.outer) stops when
+ * ||b - A u||_2 / ||b||_2 < rtol or after maxit preconditioner applications
+ * (rtol = 0 runs exactly maxit).  info: host array of nrhs entries or null.
+ * HH_ENOTCONV if some right-hand side did not converge. */
+hh_status hh_solve(hh_ctx* c, int32_t nrhs, const void* f, const void* g, void* u, double rtol, int32_t maxit,
+                   hh_solve_info* info);
+
+/* y = A x (mode 0) or y = b - A x (mode 1, b device c128) for nrhs vectors of
+ * the whole-domain operator.  Device c128 [nrhs][(N+1)^dim]. */
+hh_status hh_apply_operator(hh_ctx* c, int32_t nrhs, const void* x, const void* b, void* y, int32_t mode);
+
+/* z = B(r): one two-level step of eqs. (sub1)-(coarse1) from zero, including
+ * the hierarchy below.  Device c128 [nrhs][(N+1)^dim]. */
+hh_status hh_precondition(hh_ctx* c, int32_t nrhs, const void* r, void* z);
+
+/* Copies out the coarse data of parent box `parent` at level `level` (the
+ * parent's children are the boxes of level+1): n_c (host int), and when the
+ * pointers are non-null, A_c (host c128, n_c x n_c column-major), and the
+ * singular values of the sketch of each child (host doubles, s_i per child in
+ * child order).  A_c is returned before inversion. */
+hh_status hh_get_coarse(hh_ctx* c, int32_t level, int32_t parent, int32_t* n_c, void* Ac_host, double* sigma_host);
+
+/* Copies out the coarse block C_i of box i of level `level` (children of some
+ * parent at level-1) on the box's owned nodes: host c128, r_i columns of
+ * n_own entries (owned box p-major).  n_own and r_i returned when non-null. */
+hh_status hh_get_basis(hh_ctx* c, int32_t level, int32_t box, int32_t* n_own, int32_t* r_i, void* C_host);
+
+hh_status hh_destroy(hh_ctx* c);
+const char* hh_last_error(const hh_ctx* c);
+const char* hh_status_string(hh_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELMDD_H */

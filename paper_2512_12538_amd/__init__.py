@@ -1,0 +1,246 @@
+"""Python binding of libhelmdd (hierarchical ORAS + randomised-SVD coarse spaces, HIP/gfx950).
+
+Argument marshalling only: every function forwards to the C ABI of
+``include/helmdd.h`` with the same name.  Device arrays are torch tensors on
+the GPU (complex128, contiguous); PyTorch provides device memory and the
+stream, nothing else.  Importing this module loads the in-tree
+``libhelmdd.so``; if it has not been built the import fails loudly.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # load torch's HIP runtime first so the library shares it
+
+__all__ = [
+    "HelmddError", "hh_setup", "hh_level_info", "hh_build_coarse", "hh_solve", "hh_apply_operator",
+    "hh_precondition", "hh_get_coarse", "hh_get_basis", "hh_destroy", "decomposition", "library_path",
+    "HH_FP64", "HH_MIXED", "HH_STATIONARY", "HH_GMRES", "Context",
+]
+
+HH_OK, HH_EINVAL, HH_ENOMEM, HH_EDEVICE, HH_ENOTCONV, HH_ESINGULAR, HH_ESTATE, HH_EUNSUPPORTED = range(8)
+HH_FP64, HH_MIXED = 0, 1
+HH_STATIONARY, HH_GMRES = 0, 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def library_path() -> str:
+    return os.path.join(_HERE, "libhelmdd.so")
+
+
+class hh_operator(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("n_cells", ctypes.c_int32),
+                ("k", ctypes.POINTER(ctypes.c_double)), ("k_const", ctypes.c_double)]
+
+
+class hh_decomposition(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("m", (ctypes.c_int32 * 2) * 8),
+                ("overlap_cells", ctypes.c_int32 * 8), ("inner_iters", ctypes.c_int32 * 8)]
+
+
+class hh_options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("gmres_restart", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+
+
+class hh_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
+
+
+class HelmddError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+
+
+_STATUS = ["HH_OK", "HH_EINVAL", "HH_ENOMEM", "HH_EDEVICE", "HH_ENOTCONV", "HH_ESINGULAR", "HH_ESTATE",
+           "HH_EUNSUPPORTED"]
+
+
+def _status_name(s: int) -> str:
+    return _STATUS[s] if 0 <= s < len(_STATUS) else f"status {s}"
+
+
+def _load():
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2512_12538_amd.build`")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    sig = {
+        "hh_setup": [ctypes.POINTER(hh_operator), ctypes.POINTER(hh_decomposition), ctypes.POINTER(hh_options),
+                     ctypes.POINTER(P)],
+        "hh_level_info": [P, i32, i32, i32, P, P, P, P],
+        "hh_build_coarse": [P, i32, i32, i32, P],
+        "hh_solve": [P, i32, P, P, P, ctypes.c_double, i32, P],
+        "hh_apply_operator": [P, i32, P, P, P, i32],
+        "hh_precondition": [P, i32, P, P],
+        "hh_get_coarse": [P, i32, i32, P, P, P],
+        "hh_get_basis": [P, i32, i32, P, P, P],
+        "hh_destroy": [P],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.hh_last_error.argtypes = [P]
+    lib.hh_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+_lib = _load()
+
+
+def _check(status: int, ctx=None) -> None:
+    if status != HH_OK:
+        msg = _lib.hh_last_error(ctx).decode() if ctx else ""
+        raise HelmddError(status, msg)
+
+
+def _dev(t: torch.Tensor | None) -> ctypes.c_void_p | None:
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.complex128 or not t.is_contiguous():
+        raise ValueError("device arrays must be contiguous complex128 tensors on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def decomposition(m, overlap, inner_iters=None) -> hh_decomposition:
+    """[m_x1 x m_y1, ...] splits, overlaps delta/h (cells) and n_i per level."""
+    d = hh_decomposition()
+    d.levels = len(m)
+    for l, mm in enumerate(m):
+        d.m[l][0] = int(mm[0])
+        d.m[l][1] = int(mm[1]) if len(mm) > 1 else 1
+        d.overlap_cells[l] = int(overlap[l])
+        d.inner_iters[l] = int(inner_iters[l]) if inner_iters else 1
+    return d
+
+
+class Context:
+    """Handle of a solver context plus the sizes the binding checks arrays against."""
+
+    def __init__(self, handle: ctypes.c_void_p, dim: int, n_cells: int):
+        self.handle = handle
+        self.dim = dim
+        self.n_cells = n_cells
+        self.n = (n_cells + 1) ** dim
+
+    @property
+    def _as_parameter_(self):
+        return self.handle
+
+
+def _vectors(ctx: Context, t: torch.Tensor, name: str) -> int:
+    if t.numel() % ctx.n != 0 or t.numel() == 0:
+        raise ValueError(f"{name} must hold nrhs x {ctx.n} entries, got {tuple(t.shape)}")
+    return t.numel() // ctx.n
+
+
+def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int = HH_FP64,
+             outer: int = HH_GMRES, gmres_restart: int = 50, stream: torch.cuda.Stream | None = None):
+    """Returns a Context.  ``k`` is a float or a host array of node wavenumbers."""
+    op = hh_operator()
+    op.dim = dim
+    op.n_cells = n_cells
+    keep = None
+    if np.isscalar(k):
+        op.k = None
+        op.k_const = float(k)
+    else:
+        keep = np.ascontiguousarray(k, dtype=np.float64)
+        op.k = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        op.k_const = 0.0
+    opts = hh_options()
+    opts.precision = precision
+    opts.outer = outer
+    opts.gmres_restart = gmres_restart
+    st = stream if stream is not None else torch.cuda.current_stream()
+    opts.stream = ctypes.c_void_p(st.cuda_stream)
+    ctx = ctypes.c_void_p()
+    if keep is not None and keep.size != (n_cells + 1) ** dim:
+        raise ValueError("k must hold one value per node")
+    _check(_lib.hh_setup(ctypes.byref(op), ctypes.byref(decomp), ctypes.byref(opts), ctypes.byref(ctx)))
+    del keep
+    return Context(ctx, dim, n_cells)
+
+
+def hh_level_info(ctx, level: int, rank: int = 0, oversample: int = 0):
+    """(m_in, r, s) arrays of the boxes of a level."""
+    nb = ctypes.c_int32()
+    _check(_lib.hh_level_info(ctx, level, rank, oversample, ctypes.byref(nb), None, None, None), ctx)
+    m_in = np.zeros(nb.value, np.int32)
+    r = np.zeros(nb.value, np.int32)
+    s = np.zeros(nb.value, np.int32)
+    _check(_lib.hh_level_info(ctx, level, rank, oversample, None, m_in.ctypes.data_as(ctypes.c_void_p),
+                              r.ctypes.data_as(ctypes.c_void_p), s.ctypes.data_as(ctypes.c_void_p)), ctx)
+    return m_in, r, s
+
+
+def hh_build_coarse(ctx, level: int, rank: int, oversample: int, omega: torch.Tensor | None) -> None:
+    """``omega``: the level's Gaussian blocks concatenated (block i: m_in x s_i column-major)."""
+    m_in, _, s = hh_level_info(ctx, level, rank, oversample)
+    need = int(np.sum(m_in.astype(np.int64) * s))
+    if need > 0 and (omega is None or omega.numel() != need):
+        raise ValueError(f"omega must hold {need} entries for level {level}")
+    _check(_lib.hh_build_coarse(ctx, level, rank, oversample, _dev(omega) if need > 0 else None), ctx)
+
+
+def hh_solve(ctx, f: torch.Tensor, u: torch.Tensor, rtol: float, maxit: int, g: torch.Tensor | None = None,
+             raise_on_notconv: bool = False):
+    """Solves for the rows of f (nrhs x n) into u.  Returns a list of (iters, converged, rel_residual)."""
+    nrhs = _vectors(ctx, f, "f")
+    if u.numel() != f.numel() or (g is not None and g.numel() != f.numel()):
+        raise ValueError("u (and g) must match f")
+    info = (hh_solve_info * nrhs)()
+    st = _lib.hh_solve(ctx, nrhs, _dev(f), _dev(g), _dev(u), float(rtol), int(maxit), info)
+    if st != HH_OK and not (st == HH_ENOTCONV and not raise_on_notconv):
+        _check(st, ctx)
+    return [(info[i].iters, bool(info[i].converged), info[i].rel_residual) for i in range(nrhs)]
+
+
+def hh_apply_operator(ctx, x: torch.Tensor, y: torch.Tensor, b: torch.Tensor | None = None) -> None:
+    nrhs = _vectors(ctx, x, "x")
+    if y.numel() != x.numel() or (b is not None and b.numel() != x.numel()):
+        raise ValueError("y (and b) must match x")
+    _check(_lib.hh_apply_operator(ctx, nrhs, _dev(x), _dev(b), _dev(y), 0 if b is None else 1), ctx)
+
+
+def hh_precondition(ctx, r: torch.Tensor, z: torch.Tensor) -> None:
+    nrhs = _vectors(ctx, r, "r")
+    if z.numel() != r.numel():
+        raise ValueError("z must match r")
+    _check(_lib.hh_precondition(ctx, nrhs, _dev(r), _dev(z)), ctx)
+
+
+def hh_get_coarse(ctx, level: int, parent: int, with_sigma_len: int | None = None):
+    """(A_c as a complex128 numpy array, sketch singular values) of a parent problem."""
+    nc = ctypes.c_int32()
+    _check(_lib.hh_get_coarse(ctx, level, parent, ctypes.byref(nc), None, None), ctx)
+    Ac = np.zeros((nc.value, nc.value), dtype=np.complex128, order="F")
+    sig = np.zeros(with_sigma_len or 0, dtype=np.float64)
+    _check(_lib.hh_get_coarse(ctx, level, parent, None, Ac.ctypes.data_as(ctypes.c_void_p) if nc.value else None,
+                              sig.ctypes.data_as(ctypes.c_void_p) if sig.size else None), ctx)
+    return Ac, sig
+
+
+def hh_get_basis(ctx, level: int, box: int) -> np.ndarray:
+    """C_i on the owned nodes: complex128 array (r_i, n_own)."""
+    n_own = ctypes.c_int32()
+    r = ctypes.c_int32()
+    _check(_lib.hh_get_basis(ctx, level, box, ctypes.byref(n_own), ctypes.byref(r), None), ctx)
+    C = np.zeros((r.value, n_own.value), dtype=np.complex128)
+    if r.value:
+        _check(_lib.hh_get_basis(ctx, level, box, None, None, C.ctypes.data_as(ctypes.c_void_p)), ctx)
+    return C
+
+
+def hh_destroy(ctx) -> None:
+    if ctx is not None and ctx.handle:
+        _check(_lib.hh_destroy(ctx))
+        ctx.handle = ctypes.c_void_p()

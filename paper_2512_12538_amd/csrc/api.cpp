@@ -1,0 +1,971 @@
+// C ABI and host orchestration of the hierarchical ORAS solver.
+//
+// The host only decides what runs: it builds the integer tables of the
+// decomposition, sizes the device buffers and enqueues kernels; every
+// floating-point step (factorisations, stencils, solves, QR, SVD, Galerkin
+// products, inversions, Krylov updates) runs in the HIP kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/helmdd.h"
+#include "geometry.h"
+#include "kernels.h"
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Level {
+  int nbox = 0;
+  std::vector<BoxDev> hb;
+  BoxDev* d = nullptr;
+  long long total = 0;  // sum of box sizes
+  int max_n = 0, max_nx = 0, max_ny = 0, max_own = 0;
+  int* d_if = nullptr;
+  std::vector<long long> if_off;  // per box
+  // --- this level's boxes as children of a coarse space (built by build_coarse(level))
+  bool built = false;
+  int rank = 0, rmax = 0, smax = 0;
+  std::vector<std::vector<TraceRow>> rows;
+  std::vector<std::vector<AdjEntry>> adj;
+  bool tables = false;
+  int2* d_rows = nullptr;
+  int* d_seg_ptr = nullptr;
+  int* d_seg_y = nullptr;
+  int4* d_adj = nullptr;
+  int max_tr = 0;
+  c128* C = nullptr;
+  c128* AC = nullptr;
+  int4* d_dil = nullptr;
+  int max_dil = 0;
+  int4* d_pairs = nullptr;
+  int npairs = 0;
+  std::vector<double> sigma;       // per box, smax entries
+  // --- this level's boxes as parents (coarse space of their problems)
+  std::vector<ParentDev> hp;
+  ParentDev* dp = nullptr;
+  int max_nc = 0;
+  bool has_coarse = false;
+  c128* Ainv = nullptr;
+  c128* Araw = nullptr;
+  int* d_piv = nullptr;
+  long long nc_total = 0, nc2_total = 0;
+  // --- work buffers, capacity qcap columns
+  int qcap = 0;
+  c128 *R = nullptr, *X = nullptr, *T = nullptr, *E = nullptr, *U = nullptr;
+  c128 *cvec = nullptr, *yvec = nullptr;
+};
+
+}  // namespace
+
+struct hh_ctx {
+  std::string err;
+  bool poisoned = false;
+  hipStream_t stream = nullptr;
+  int precision = HH_FP64;
+  int outer = HH_GMRES;
+  int restart = 50;
+  Geometry geo;
+  OpDev op{};
+  double* d_k = nullptr;
+  int L = 0;
+  std::vector<int> inner;
+  std::vector<Level> lv;
+  c128* G = nullptr;  // FP64 leaf factors
+  c64* G32 = nullptr; // complex64 copy (mixed)
+  long long g_total = 0;
+  int* d_info = nullptr;
+  // outer-loop buffers
+  std::vector<DevBuf> scratch;
+  c128* d_partial = nullptr;
+  size_t partial_cap = 0;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+#define HH_CHECK(expr)                                                   \
+  do {                                                                   \
+    hipError_t e_ = (expr);                                              \
+    if (e_ != hipSuccess) return device_fail(c, #expr, e_);              \
+  } while (0)
+
+#define HH_TRY(expr)                       \
+  do {                                     \
+    hh_status s_ = (expr);                 \
+    if (s_ != HH_OK) return s_;            \
+  } while (0)
+
+hh_status device_fail(hh_ctx* c, const char* what, hipError_t e) {
+  c->poisoned = true;
+  c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return HH_EDEVICE;
+}
+
+hh_status fail(hh_ctx* c, hh_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+template <typename T>
+hh_status dalloc(hh_ctx* c, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return HH_OK;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, HH_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+  }
+  c->allocs.push_back(q);
+  *p = reinterpret_cast<T*>(q);
+  return HH_OK;
+}
+
+void dfree(hh_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
+  if (it != c->allocs.end()) c->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+template <typename T>
+hh_status upload(hh_ctx* c, T** dst, const std::vector<T>& src) {
+  if (*dst) {
+    dfree(c, *dst);
+    *dst = nullptr;
+  }
+  if (src.empty()) return HH_OK;
+  HH_TRY(dalloc(c, dst, src.size()));
+  HH_CHECK(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+  HH_CHECK(hipStreamSynchronize(c->stream));
+  return HH_OK;
+}
+
+hh_status sync(hh_ctx* c) {
+  HH_CHECK(hipStreamSynchronize(c->stream));
+  return HH_OK;
+}
+
+hh_status push_boxes(hh_ctx* c, Level& L) { return upload(c, &L.d, L.hb); }
+
+// Grow the work buffers of levels lo..L to hold q columns.
+hh_status ensure_work(hh_ctx* c, int lo, int q) {
+  for (int l = lo; l <= c->L; ++l) {
+    Level& L = c->lv[l];
+    if (L.qcap >= q) continue;
+    for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec}) {
+      dfree(c, *b);
+      *b = nullptr;
+    }
+    const size_t n = (size_t)L.total * q;
+    HH_TRY(dalloc(c, &L.R, n));
+    HH_TRY(dalloc(c, &L.X, n));
+    HH_TRY(dalloc(c, &L.T, n));
+    HH_TRY(dalloc(c, &L.E, n));
+    HH_TRY(dalloc(c, &L.U, n));
+    if (L.nc_total > 0) {
+      HH_TRY(dalloc(c, &L.cvec, (size_t)L.nc_total * q));
+      HH_TRY(dalloc(c, &L.yvec, (size_t)L.nc_total * q));
+    }
+    L.qcap = q;
+  }
+  return HH_OK;
+}
+
+hh_status ensure_partial(hh_ctx* c, size_t count) {
+  if (c->partial_cap >= count) return HH_OK;
+  dfree(c, c->d_partial);
+  c->d_partial = nullptr;
+  HH_TRY(dalloc(c, &c->d_partial, count));
+  c->partial_cap = count;
+  return HH_OK;
+}
+
+// ------------------------------------------------------------------ the sweeps
+hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x);
+
+// out = B_l(r) for every box of level l: smoother over the children, then the
+// coarse correction of each box's own coarse space (eqs. (sub1)-(coarse1)).
+hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
+  Level& P = c->lv[l];
+  Level& Ch = c->lv[l + 1];
+  HH_CHECK(launch_gather_children(Ch.d, Ch.nbox, Ch.max_n, P.d, q, r, Ch.R, c->stream));
+  HH_TRY(solve_level(c, l + 1, q, Ch.R, Ch.X));
+  HH_CHECK(launch_scatter_owned(Ch.d, Ch.nbox, Ch.max_own, P.d, q, Ch.X, out, c->stream));
+  if (P.has_coarse) {
+    HH_CHECK(launch_apply_box(c->op, P.d, P.nbox, P.max_n, q, out, r, P.T, 1, c->stream));
+    HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, P.d, P.dp, Ch.rmax, q, Ch.C, P.T, P.cvec, c->stream));
+    HH_CHECK(launch_coarse_gemv(P.dp, P.nbox, P.max_nc, q, P.Ainv, P.cvec, P.yvec, c->stream));
+    HH_CHECK(launch_coarse_prolong(Ch.d, Ch.nbox, Ch.max_own, P.d, P.dp, q, Ch.C, P.yvec, out, c->stream));
+  }
+  return HH_OK;
+}
+
+// x = S_l(rhs) for every box of level l >= 1: exact leaf solve, or n_i
+// two-level steps from zero on the box problem.
+hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x) {
+  Level& Lv = c->lv[l];
+  if (l == c->L) {
+    if (c->precision == HH_MIXED) {
+      HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, c->stream));
+    } else {
+      HH_CHECK(launch_leaf_solve<double>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G, rhs, x, c->stream));
+    }
+    return HH_OK;
+  }
+  const int ni = std::max(1, c->inner[l]);
+  HH_TRY(two_level(c, l, q, rhs, x));
+  for (int it = 1; it < ni; ++it) {
+    HH_CHECK(launch_apply_box(c->op, Lv.d, Lv.nbox, Lv.max_n, q, x, rhs, Lv.E, 1, c->stream));
+    HH_TRY(two_level(c, l, q, Lv.E, Lv.U));
+    HH_CHECK(launch_add_masked(Lv.U, x, (long long)Lv.total * q, 1, nullptr, c->stream));
+  }
+  return HH_OK;
+}
+
+hh_status check_usable(hh_ctx* c) {
+  if (!c) return HH_EINVAL;
+  if (c->poisoned) return fail(c, HH_EDEVICE, "context poisoned by an earlier device error: " + c->err);
+  return HH_OK;
+}
+
+hh_status check_built(hh_ctx* c) {
+  for (int l = 1; l <= c->L; ++l)
+    if (!c->lv[l].built) return fail(c, HH_ESTATE, "hh_build_coarse has not run for level " + std::to_string(l));
+  return HH_OK;
+}
+
+// Device norms of q columns of length n: out[b] = ||x_b||_2 on the host.
+hh_status norms(hh_ctx* c, int q, long long n, const c128* x, c128* dtmp, std::vector<double>& out) {
+  HH_TRY(ensure_partial(c, (size_t)q * multidot_nblocks(n)));
+  HH_CHECK(launch_multidot(1, q, n, x, 0, x, c->d_partial, dtmp, c->stream));
+  std::vector<c128> h(q);
+  HH_CHECK(hipMemcpyAsync(h.data(), dtmp, q * sizeof(c128), hipMemcpyDeviceToHost, c->stream));
+  HH_TRY(sync(c));
+  out.resize(q);
+  for (int b = 0; b < q; ++b) out[b] = std::sqrt(std::max(h[b].x, 0.0));
+  return HH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hh_status_string(hh_status s) {
+  switch (s) {
+    case HH_OK: return "HH_OK";
+    case HH_EINVAL: return "HH_EINVAL";
+    case HH_ENOMEM: return "HH_ENOMEM";
+    case HH_EDEVICE: return "HH_EDEVICE";
+    case HH_ENOTCONV: return "HH_ENOTCONV";
+    case HH_ESINGULAR: return "HH_ESINGULAR";
+    case HH_ESTATE: return "HH_ESTATE";
+    case HH_EUNSUPPORTED: return "HH_EUNSUPPORTED";
+  }
+  return "unknown";
+}
+
+const char* hh_last_error(const hh_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+hh_status hh_destroy(hh_ctx* c) {
+  if (!c) return HH_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  delete c;
+  return HH_OK;
+}
+
+hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_options* o, hh_ctx** out) {
+  if (!A || !d || !out) return HH_EINVAL;
+  *out = nullptr;
+  if (A->dim != 1 && A->dim != 2) return HH_EINVAL;
+  if (A->n_cells < 2 || A->n_cells > (1 << 15)) return HH_EINVAL;
+  const long long N1 = A->n_cells + 1;
+  const long long nn = A->dim == 2 ? N1 * N1 : N1;
+  if (A->k) {
+    for (long long i = 0; i < nn; ++i)
+      if (!std::isfinite(A->k[i]) || A->k[i] < 0.0) return HH_EINVAL;
+  } else if (!std::isfinite(A->k_const) || A->k_const < 0.0) {
+    return HH_EINVAL;
+  }
+  hh_ctx* c = new (std::nothrow) hh_ctx();
+  if (!c) return HH_ENOMEM;
+  if (o) {
+    c->stream = reinterpret_cast<hipStream_t>(o->stream);
+    c->precision = o->precision == HH_MIXED ? HH_MIXED : HH_FP64;
+    c->outer = o->outer == HH_STATIONARY ? HH_STATIONARY : HH_GMRES;
+    c->restart = o->gmres_restart > 0 ? o->gmres_restart : 50;
+  }
+  std::string msg = build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, c->geo);
+  if (!msg.empty()) {
+    delete c;
+    return HH_EINVAL;
+  }
+  c->L = d->levels;
+  c->inner.assign(c->L + 1, 1);
+  for (int l = 1; l <= c->L; ++l) c->inner[l] = d->inner_iters[l - 1] > 0 ? d->inner_iters[l - 1] : 1;
+  hh_status st = HH_OK;
+  auto bail = [&](hh_status s) {
+    hh_destroy(c);
+    return s;
+  };
+  // operator
+  c->op.kc = A->k_const;
+  c->op.h = 1.0 / A->n_cells;
+  c->op.ih2 = (double)A->n_cells * (double)A->n_cells;
+  c->op.N1 = (int)N1;
+  c->op.dim = A->dim;
+  if (A->k) {
+    std::vector<double> kv(A->k, A->k + nn);
+    if ((st = upload(c, &c->d_k, kv)) != HH_OK) return bail(st);
+  }
+  c->op.k = c->d_k;
+  // levels
+  c->lv.resize(c->L + 1);
+  for (int l = 0; l <= c->L; ++l) {
+    Level& Lv = c->lv[l];
+    const std::vector<HBox>& gb = c->geo.levels[l];
+    Lv.nbox = (int)gb.size();
+    Lv.hb.resize(Lv.nbox);
+    std::vector<int> ifidx;
+    long long off = 0;
+    for (int i = 0; i < Lv.nbox; ++i) {
+      const HBox& h = gb[i];
+      BoxDev& b = Lv.hb[i];
+      std::memset(&b, 0, sizeof(b));
+      b.p0 = h.p0; b.p1 = h.p1; b.q0 = h.q0; b.q1 = h.q1;
+      b.op0 = h.op0; b.op1 = h.op1; b.oq0 = h.oq0; b.oq1 = h.oq1;
+      b.nx = h.nx(); b.ny = h.ny(); b.n = h.n();
+      b.parent = h.parent < 0 ? 0 : h.parent;
+      if (l > 0) {
+        const HBox& ph = c->geo.levels[l - 1][h.parent];
+        b.pp0 = ph.p0; b.pq0 = ph.q0; b.pny = ph.ny();
+      }
+      b.m_in = (int)h.iface.size();
+      b.if_off = (int)ifidx.size();
+      ifidx.insert(ifidx.end(), h.iface.begin(), h.iface.end());
+      b.n_own = h.n_own();
+      b.own_ny = h.oq1 - h.oq0 + 1;
+      b.voff = off;
+      off += b.n;
+      Lv.max_n = std::max(Lv.max_n, b.n);
+      Lv.max_nx = std::max(Lv.max_nx, b.nx);
+      Lv.max_ny = std::max(Lv.max_ny, b.ny);
+      Lv.max_own = std::max(Lv.max_own, b.n_own);
+    }
+    Lv.total = off;
+    if ((st = upload(c, &Lv.d_if, ifidx)) != HH_OK) return bail(st);
+  }
+  // leaf factor storage
+  Level& leaf = c->lv[c->L];
+  if (leaf.max_ny > 256) {
+    c->err = "leaf boxes wider than 256 nodes along q are not supported";
+    hh_destroy(c);
+    return HH_EUNSUPPORTED;
+  }
+  long long goff = 0;
+  for (BoxDev& b : leaf.hb) {
+    b.goff = goff;
+    goff += (long long)b.nx * b.ny * b.ny;
+  }
+  c->g_total = goff;
+  for (int l = 0; l <= c->L; ++l)
+    if ((st = push_boxes(c, c->lv[l])) != HH_OK) return bail(st);
+  if ((st = dalloc(c, &c->G, (size_t)goff)) != HH_OK) return bail(st);
+  if ((st = dalloc(c, &c->d_info, (size_t)std::max(leaf.nbox, 4096))) != HH_OK) return bail(st);
+  if (launch_leaf_factor(c->op, leaf.d, leaf.nbox, leaf.max_ny, c->G, c->d_info, c->stream) != hipSuccess)
+    return bail(device_fail(c, "leaf factor", hipGetLastError()));
+  std::vector<int> info(leaf.nbox);
+  if (hipMemcpyAsync(info.data(), c->d_info, leaf.nbox * sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
+          hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(device_fail(c, "leaf factor sync", hipGetLastError()));
+  for (int i = 0; i < leaf.nbox; ++i)
+    if (info[i] != 0) {
+      c->err = "zero pivot in the factorisation of leaf " + std::to_string(i);
+      hh_destroy(c);
+      return HH_ESINGULAR;
+    }
+  if (c->precision == HH_MIXED) {
+    if ((st = dalloc(c, &c->G32, (size_t)goff)) != HH_OK) return bail(st);
+    if (launch_f64_to_f32(c->G, c->G32, goff, c->stream) != hipSuccess)
+      return bail(device_fail(c, "convert", hipGetLastError()));
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(device_fail(c, "sync", hipGetLastError()));
+    dfree(c, c->G);
+    c->G = nullptr;
+  }
+  *out = c;
+  return HH_OK;
+}
+
+hh_status hh_level_info(const hh_ctx* cc, int32_t level, int32_t rank, int32_t oversample, int32_t* n_boxes,
+                        int32_t* m_in, int32_t* r, int32_t* s) {
+  if (!cc) return HH_EINVAL;
+  if (level < 0 || level > cc->L || rank < 0 || oversample < 0) return HH_EINVAL;
+  const std::vector<HBox>& gb = cc->geo.levels[level];
+  if (n_boxes) *n_boxes = (int32_t)gb.size();
+  for (size_t i = 0; i < gb.size(); ++i) {
+    const int mi = (int)gb[i].iface.size();
+    const long long rr = std::min<long long>((long long)rank * gb[i].n_if, mi);
+    const long long ss = rr > 0 ? std::min<long long>(rr + oversample, mi) : 0;
+    if (m_in) m_in[i] = mi;
+    if (r) r[i] = (int32_t)rr;
+    if (s) s[i] = (int32_t)ss;
+  }
+  return HH_OK;
+}
+
+hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversample, const void* omega) {
+  HH_TRY(check_usable(c));
+  if (level < 1 || level > c->L || rank < 0 || oversample < 0)
+    return fail(c, HH_EINVAL, "level must be in 1..levels; rank and oversample non-negative");
+  if (level < c->L && !c->lv[level + 1].built)
+    return fail(c, HH_ESTATE, "build the coarse spaces from the finest level up");
+  Level& Lv = c->lv[level];
+  Level& P = c->lv[level - 1];
+  const std::vector<HBox>& gb = c->geo.levels[level];
+  const std::vector<HBox>& pgb = c->geo.levels[level - 1];
+  // ranks and sketch widths
+  int rmax = 0, smax = 0;
+  for (int i = 0; i < Lv.nbox; ++i) {
+    const int mi = (int)gb[i].iface.size();
+    const int rr = (int)std::min<long long>((long long)rank * gb[i].n_if, mi);
+    const int ss = rr > 0 ? (int)std::min<long long>((long long)rr + oversample, mi) : 0;
+    Lv.hb[i].r = rr;
+    Lv.hb[i].s = ss;
+    rmax = std::max(rmax, rr);
+    smax = std::max(smax, ss);
+  }
+  if (smax > 128) return fail(c, HH_EUNSUPPORTED, "sketch width above 128 is not supported");
+  if (rmax > 0 && !omega) return fail(c, HH_EINVAL, "omega is required when the rank is positive");
+  // invalidate every coarser level: their sub-solves change with this one
+  for (int l = 1; l < level; ++l) c->lv[l].built = false;
+  Lv.rank = rank;
+  Lv.rmax = rmax;
+  Lv.smax = smax;
+  // parents' coarse layout
+  P.hp.assign(P.nbox, ParentDev{});
+  long long nc_tot = 0, nc2 = 0;
+  int max_nc = 0;
+  for (int p = 0; p < P.nbox; ++p) {
+    ParentDev& pd = P.hp[p];
+    const HBox& ph = pgb[p];
+    int nc = 0;
+    pd.child0 = ph.children.empty() ? 0 : ph.children.front();
+    pd.nchild = (int)ph.children.size();
+    for (int ch : ph.children) {
+      Lv.hb[ch].cidx = nc;
+      nc += Lv.hb[ch].r;
+    }
+    pd.n_c = nc;
+    pd.aoff = nc2;
+    pd.yoff = nc_tot;
+    nc2 += (long long)nc * nc;
+    nc_tot += nc;
+    max_nc = std::max(max_nc, nc);
+  }
+  for (c128** b : {&P.Ainv, &P.Araw, &P.cvec, &P.yvec}) {
+    dfree(c, *b);
+    *b = nullptr;
+  }
+  dfree(c, P.d_piv);
+  P.d_piv = nullptr;
+  dfree(c, Lv.C);
+  Lv.C = nullptr;
+  dfree(c, Lv.AC);
+  Lv.AC = nullptr;
+  P.nc_total = nc_tot;
+  P.nc2_total = nc2;
+  P.max_nc = max_nc;
+  P.has_coarse = false;
+  P.qcap = 0;  // forces cvec/yvec reallocation with the new size
+  Lv.sigma.assign((size_t)Lv.nbox * std::max(smax, 1), 0.0);
+  if (rmax == 0) {
+    HH_TRY(push_boxes(c, Lv));
+    HH_TRY(upload(c, &P.dp, P.hp));
+    Lv.built = true;
+    return HH_OK;
+  }
+  // trace tables (geometry only; cached)
+  if (!Lv.tables) {
+    Lv.rows.resize(Lv.nbox);
+    Lv.adj.resize(Lv.nbox);
+    for (int i = 0; i < Lv.nbox; ++i) trace_tables(c->geo, level, i, Lv.rows[i], Lv.adj[i]);
+    std::vector<int2> rows;
+    std::vector<int> seg_ptr, seg_y;
+    std::vector<int4> adj;
+    for (int i = 0; i < Lv.nbox; ++i) {
+      Lv.hb[i].tr_off = (int)rows.size();
+      Lv.hb[i].tr_cnt = (int)Lv.rows[i].size();
+      Lv.max_tr = std::max(Lv.max_tr, Lv.hb[i].tr_cnt);
+      for (const TraceRow& t : Lv.rows[i]) rows.push_back(make_int2(t.j, t.xl));
+      Lv.hb[i].adj_off = (int)seg_y.size();
+      int prev = -1;
+      for (const AdjEntry& e : Lv.adj[i]) {
+        if (e.yl != prev) {
+          seg_ptr.push_back((int)adj.size());
+          seg_y.push_back(e.yl);
+          prev = e.yl;
+        }
+        adj.push_back(make_int4(e.row, e.dp, e.dq, 0));
+      }
+      Lv.hb[i].adj_cnt = (int)seg_y.size() - Lv.hb[i].adj_off;
+    }
+    seg_ptr.push_back((int)adj.size());
+    HH_TRY(upload(c, &Lv.d_rows, rows));
+    HH_TRY(upload(c, &Lv.d_seg_ptr, seg_ptr));
+    HH_TRY(upload(c, &Lv.d_seg_y, seg_y));
+    HH_TRY(upload(c, &Lv.d_adj, adj));
+    Lv.tables = true;
+  }
+  // coarse block storage, dilated owned boxes, Galerkin pairs
+  long long coff = 0, acoff = 0;
+  std::vector<int4> dil(Lv.nbox);
+  int max_dil = 0;
+  for (int i = 0; i < Lv.nbox; ++i) {
+    BoxDev& b = Lv.hb[i];
+    const HBox& h = gb[i];
+    const HBox& ph = pgb[h.parent];
+    b.coff = coff;
+    coff += (long long)b.r * b.n_own;
+    int4 d4;
+    d4.x = std::max(h.op0 - 1, ph.p0);
+    d4.y = std::min(h.op1 + 1, ph.p1);
+    d4.z = c->geo.dim == 2 ? std::max(h.oq0 - 1, ph.q0) : 0;
+    d4.w = c->geo.dim == 2 ? std::min(h.oq1 + 1, ph.q1) : 0;
+    dil[i] = d4;
+    const int nd = (d4.y - d4.x + 1) * (d4.w - d4.z + 1);
+    max_dil = std::max(max_dil, nd);
+    b.acoff = acoff;
+    acoff += (long long)b.r * nd;
+  }
+  std::vector<int4> pairs;
+  for (int p = 0; p < P.nbox; ++p)
+    for (int i : pgb[p].children)
+      for (int j : pgb[p].children) {
+        const HBox& hi = gb[i];
+        const int4& dj = dil[j];
+        if (hi.op0 <= dj.y && dj.x <= hi.op1 && hi.oq0 <= dj.w && dj.z <= hi.oq1 && Lv.hb[i].r > 0 &&
+            Lv.hb[j].r > 0)
+          pairs.push_back(make_int4(i, j, p, 0));
+      }
+  Lv.max_dil = max_dil;
+  Lv.npairs = (int)pairs.size();
+  HH_TRY(upload(c, &Lv.d_dil, dil));
+  HH_TRY(upload(c, &Lv.d_pairs, pairs));
+  HH_TRY(push_boxes(c, Lv));
+  HH_TRY(upload(c, &P.dp, P.hp));
+  HH_TRY(dalloc(c, &Lv.C, (size_t)coff));
+  HH_TRY(dalloc(c, &Lv.AC, (size_t)acoff));
+  HH_TRY(dalloc(c, &P.Ainv, (size_t)nc2));
+  HH_TRY(dalloc(c, &P.Araw, (size_t)nc2));
+  HH_TRY(dalloc(c, &P.d_piv, (size_t)P.nbox * max_nc));
+  // ---------------------------------------------------------------- sketch Y = T_i Omega_i
+  HH_TRY(ensure_work(c, level - 1, std::max(smax, 1)));
+  // per-box small-matrix layouts
+  std::vector<int> qm(Lv.nbox), qn(Lv.nbox), bm(Lv.nbox), rr(Lv.nbox);
+  std::vector<long long> yoff(Lv.nbox), soff(Lv.nbox), bhoff(Lv.nbox), voff(Lv.nbox), omoff(Lv.nbox),
+      sgoff(Lv.nbox);
+  long long yt = 0, bht = 0, vt = 0, omt = 0;
+  int max_mr = 0;
+  for (int i = 0; i < Lv.nbox; ++i) {
+    const BoxDev& b = Lv.hb[i];
+    qm[i] = b.tr_cnt;
+    qn[i] = b.s;
+    bm[i] = b.m_in;
+    rr[i] = b.r;
+    yoff[i] = yt;
+    yt += (long long)b.tr_cnt * b.s;
+    soff[i] = (long long)i * smax * smax;
+    sgoff[i] = (long long)i * smax;
+    bhoff[i] = bht;
+    bht += (long long)b.m_in * b.s;
+    voff[i] = vt;
+    vt += (long long)b.m_in * b.r;
+    omoff[i] = omt;
+    omt += (long long)b.m_in * b.s;
+    max_mr = std::max(max_mr, b.m_in * std::max(b.r, 1));
+  }
+  int *d_qm = nullptr, *d_qn = nullptr, *d_bm = nullptr, *d_rr = nullptr;
+  long long *d_yoff = nullptr, *d_soff = nullptr, *d_bhoff = nullptr, *d_voff = nullptr, *d_omoff = nullptr,
+            *d_sgoff = nullptr;
+  c128 *Y = nullptr, *Wk = nullptr, *Rs = nullptr, *Us = nullptr, *BH = nullptr, *V = nullptr;
+  double* d_sig = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : std::initializer_list<void*>{d_qm, d_qn, d_bm, d_rr, d_yoff, d_soff, d_bhoff, d_voff, d_omoff,
+                                                d_sgoff, Y, Wk, Rs, Us, BH, V, d_sig})
+      dfree(c, p);
+  };
+  hh_status st = HH_OK;
+  do {
+    if ((st = upload(c, &d_qm, qm)) != HH_OK) break;
+    if ((st = upload(c, &d_qn, qn)) != HH_OK) break;
+    if ((st = upload(c, &d_bm, bm)) != HH_OK) break;
+    if ((st = upload(c, &d_rr, rr)) != HH_OK) break;
+    if ((st = upload(c, &d_yoff, yoff)) != HH_OK) break;
+    if ((st = upload(c, &d_soff, soff)) != HH_OK) break;
+    if ((st = upload(c, &d_sgoff, sgoff)) != HH_OK) break;
+    if ((st = upload(c, &d_bhoff, bhoff)) != HH_OK) break;
+    if ((st = upload(c, &d_voff, voff)) != HH_OK) break;
+    if ((st = upload(c, &d_omoff, omoff)) != HH_OK) break;
+    const size_t ysz = std::max<long long>(yt, bht);
+    if ((st = dalloc(c, &Y, ysz)) != HH_OK) break;
+    if ((st = dalloc(c, &Wk, ysz)) != HH_OK) break;
+    if ((st = dalloc(c, &Rs, (size_t)Lv.nbox * smax * smax)) != HH_OK) break;
+    if ((st = dalloc(c, &Us, (size_t)Lv.nbox * smax * smax)) != HH_OK) break;
+    if ((st = dalloc(c, &BH, (size_t)std::max<long long>(bht, 1))) != HH_OK) break;
+    if ((st = dalloc(c, &V, (size_t)std::max<long long>(vt, 1))) != HH_OK) break;
+    if ((st = dalloc(c, &d_sig, (size_t)Lv.nbox * smax)) != HH_OK) break;
+  } while (false);
+  if (st != HH_OK) {
+    cleanup();
+    return st;
+  }
+  const c128* Om = reinterpret_cast<const c128*>(omega);
+  hipStream_t s = c->stream;
+  const int q = smax;
+  const long long nlev = Lv.total * q;
+#define BC(expr)                                    \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) {                         \
+      cleanup();                                    \
+      return device_fail(c, #expr, e_);             \
+    }                                               \
+  } while (0)
+#define BT(expr)              \
+  do {                        \
+    hh_status s2_ = (expr);   \
+    if (s2_ != HH_OK) {       \
+      cleanup();              \
+      return s2_;             \
+    }                         \
+  } while (0)
+  // X = S_i(B_i^T Omega_i)
+  BC(launch_fill_zero(Lv.R, nlev * sizeof(c128), s));
+  BC(launch_iface_scatter(Lv.d, Lv.nbox, q, Lv.d_if, d_omoff, Om, 0, Lv.R, s));
+  BT(solve_level(c, level, q, Lv.R, Lv.X));
+  // Y = stacked traces on the neighbours; Q = qr(Y)
+  BC(launch_trace(c->op, Lv.d, Lv.nbox, q, Lv.d_rows, d_yoff, Lv.X, Y, s));
+  BC(launch_qr(Lv.nbox, d_qm, d_qn, d_yoff, Y, d_soff, Rs, Wk, s));
+  // B^H = B_i conj(S_i(conj((B_i^o)^H Q)))
+  BC(launch_fill_zero(Lv.R, nlev * sizeof(c128), s));
+  BC(launch_trace_adjoint(c->op, Lv.d, Lv.nbox, q, Lv.d_rows, Lv.d_seg_ptr, Lv.d_seg_y, Lv.d_adj, d_yoff, Y, Lv.R,
+                          s));
+  BC(launch_conj_inplace(Lv.R, nlev, s));
+  BT(solve_level(c, level, q, Lv.R, Lv.X));
+  BC(launch_conj_inplace(Lv.X, nlev, s));
+  BC(launch_iface_gather(Lv.d, Lv.nbox, q, Lv.d_if, d_bhoff, Lv.X, BH, 0, s));
+  // SVD of B: B^H = Q_B R, R = U_R S V_R^H, V_i = Q_B U_R[:, :r]
+  BC(launch_qr(Lv.nbox, d_bm, d_qn, d_bhoff, BH, d_soff, Rs, Wk, s));
+  BC(launch_jacobi_svd(Lv.nbox, d_qn, d_soff, Rs, d_soff, Us, d_sig, d_sgoff, s));
+  BC(launch_small_gemm(Lv.nbox, max_mr, d_bm, d_qn, d_rr, d_bhoff, BH, d_soff, Us, d_voff, V, s));
+  // C_i = P_i S_i(B_i^T V_i)
+  BC(launch_fill_zero(Lv.R, (long long)Lv.total * rmax * sizeof(c128), s));
+  BC(launch_iface_scatter(Lv.d, Lv.nbox, rmax, Lv.d_if, d_voff, V, 1, Lv.R, s));
+  BT(solve_level(c, level, rmax, Lv.R, Lv.X));
+  BC(launch_extract_owned(Lv.d, Lv.nbox, Lv.max_own, rmax, Lv.X, Lv.C, s));
+  // A_c = C^H A_P C, then its inverse
+  BC(launch_galerkin_ac(c->op, Lv.d, Lv.nbox, P.d, Lv.d_dil, max_dil, rmax, Lv.C, Lv.AC, s));
+  BC(launch_fill_zero(P.Ainv, nc2 * sizeof(c128), s));
+  BC(launch_galerkin_blocks(Lv.d, P.dp, Lv.d_pairs, Lv.npairs, rmax, Lv.d_dil, Lv.C, Lv.AC, P.Ainv, s));
+  BC(launch_copy(P.Ainv, P.Araw, nc2, s));
+  BC(launch_gj_inverse(P.dp, P.nbox, max_nc, P.Ainv, P.d_piv, c->d_info, s));
+  std::vector<int> info(P.nbox);
+  BC(hipMemcpyAsync(info.data(), c->d_info, P.nbox * sizeof(int), hipMemcpyDeviceToHost, s));
+  BC(hipMemcpyAsync(Lv.sigma.data(), d_sig, (size_t)Lv.nbox * smax * sizeof(double), hipMemcpyDeviceToHost, s));
+  BC(hipStreamSynchronize(s));
+  cleanup();
+#undef BC
+#undef BT
+  for (int p = 0; p < P.nbox; ++p)
+    if (info[p] != 0) return fail(c, HH_ESINGULAR, "singular coarse matrix A_c of parent " + std::to_string(p));
+  P.has_coarse = nc_tot > 0;
+  Lv.built = true;
+  return HH_OK;
+}
+
+hh_status hh_apply_operator(hh_ctx* c, int32_t nrhs, const void* x, const void* b, void* y, int32_t mode) {
+  HH_TRY(check_usable(c));
+  if (nrhs <= 0 || !x || !y || (mode == 1 && !b) || (mode != 0 && mode != 1)) return fail(c, HH_EINVAL, "bad args");
+  Level& R = c->lv[0];
+  HH_CHECK(launch_apply_box(c->op, R.d, 1, R.max_n, nrhs, reinterpret_cast<const c128*>(x),
+                            reinterpret_cast<const c128*>(b), reinterpret_cast<c128*>(y), mode, c->stream));
+  return sync(c);
+}
+
+hh_status hh_precondition(hh_ctx* c, int32_t nrhs, const void* r, void* z) {
+  HH_TRY(check_usable(c));
+  if (nrhs <= 0 || !r || !z) return fail(c, HH_EINVAL, "bad args");
+  HH_TRY(check_built(c));
+  HH_TRY(ensure_work(c, 0, nrhs));
+  HH_TRY(two_level(c, 0, nrhs, reinterpret_cast<const c128*>(r), reinterpret_cast<c128*>(z)));
+  return sync(c);
+}
+
+}  // extern "C"
+
+namespace {
+
+hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit, const std::vector<double>& nb,
+                std::vector<int>& iters, std::vector<double>& relres, std::vector<int>& conv) {
+  const long long n = c->lv[0].total;
+  const int m = std::max(1, std::min(c->restart, std::max(maxit, 1)));
+  hipStream_t s = c->stream;
+  c128 *Vb = nullptr, *Zb = nullptr, *W = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+  c128 *h1 = nullptr, *h2 = nullptr, *tmp = nullptr, *y = nullptr;
+  double *hn = nullptr, *est = nullptr;
+  int *act = nullptr, *jd = nullptr;
+  auto cleanup = [&]() {
+    for (void* p : std::initializer_list<void*>{Vb, Zb, W, H, cs, sn, g, h1, h2, tmp, y, hn, est, act, jd})
+      dfree(c, p);
+  };
+  hh_status st = HH_OK;
+  do {
+    if ((st = dalloc(c, &Vb, (size_t)(m + 1) * q * n)) != HH_OK) break;
+    if ((st = dalloc(c, &Zb, (size_t)m * q * n)) != HH_OK) break;
+    if ((st = dalloc(c, &W, (size_t)q * n)) != HH_OK) break;
+    if ((st = dalloc(c, &H, (size_t)q * (m + 1) * m)) != HH_OK) break;
+    if ((st = dalloc(c, &cs, (size_t)q * m)) != HH_OK) break;
+    if ((st = dalloc(c, &sn, (size_t)q * m)) != HH_OK) break;
+    if ((st = dalloc(c, &g, (size_t)q * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &h1, (size_t)q * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &h2, (size_t)q * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &tmp, (size_t)q * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &y, (size_t)q * m)) != HH_OK) break;
+    if ((st = dalloc(c, &hn, (size_t)q)) != HH_OK) break;
+    if ((st = dalloc(c, &est, (size_t)q)) != HH_OK) break;
+    if ((st = dalloc(c, &act, (size_t)q)) != HH_OK) break;
+    if ((st = dalloc(c, &jd, (size_t)q)) != HH_OK) break;
+    if ((st = ensure_partial(c, (size_t)(m + 1) * q * multidot_nblocks(n))) != HH_OK) break;
+  } while (false);
+  if (st != HH_OK) {
+    cleanup();
+    return st;
+  }
+#define GC(expr)                                    \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) {                         \
+      cleanup();                                    \
+      return device_fail(c, #expr, e_);             \
+    }                                               \
+  } while (0)
+#define GT(expr)              \
+  do {                        \
+    hh_status s2_ = (expr);   \
+    if (s2_ != HH_OK) {       \
+      cleanup();              \
+      return s2_;             \
+    }                         \
+  } while (0)
+  const long long vs = (long long)q * n;
+  std::vector<double> beta(q);
+  std::vector<int> active(q), jdone(q);
+  // u = 0, r = b
+  GC(launch_fill_zero(u, vs * (long long)sizeof(c128), s));
+  GC(launch_copy(b, W, vs, s));
+  GT(norms(c, q, n, W, tmp, beta));
+  while (true) {
+    bool any = false;
+    for (int k = 0; k < q; ++k) {
+      relres[k] = nb[k] > 0.0 ? beta[k] / nb[k] : 0.0;
+      conv[k] = relres[k] < rtol || nb[k] == 0.0;
+      active[k] = !conv[k] && iters[k] < maxit;
+      any = any || active[k];
+      jdone[k] = 0;
+    }
+    if (!any) break;
+    // V_0 = r / beta; g = beta e_1
+    GC(launch_multidot(1, q, n, W, 0, W, c->d_partial, tmp, s));
+    GC(launch_normalize(q, n, tmp, W, Vb, nullptr, s));
+    std::vector<c128> g0((size_t)q * (m + 1), make_double2(0.0, 0.0));
+    for (int k = 0; k < q; ++k) g0[(size_t)k * (m + 1)] = make_double2(beta[k], 0.0);
+    GC(hipMemcpyAsync(g, g0.data(), g0.size() * sizeof(c128), hipMemcpyHostToDevice, s));
+    GC(hipMemcpyAsync(act, active.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
+    int j = 0;
+    for (; j < m; ++j) {
+      const c128* vj = Vb + j * vs;
+      c128* zj = Zb + j * vs;
+      GT(two_level(c, 0, q, vj, zj));
+      GC(launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, zj, nullptr, W, 0, s));
+      GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h1, s));
+      GC(launch_basis_update(j + 1, q, n, Vb, vs, h1, W, s));
+      GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h2, s));
+      GC(launch_basis_update(j + 1, q, n, Vb, vs, h2, W, s));
+      GC(launch_multidot(1, q, n, W, 0, W, c->d_partial, tmp, s));
+      GC(launch_normalize(q, n, tmp, W, Vb + (j + 1) * vs, hn, s));
+      GC(launch_gmres_step(q, j, m, H, h1, h2, hn, cs, sn, g, est, act, s));
+      std::vector<double> e(q);
+      GC(hipMemcpyAsync(e.data(), est, q * sizeof(double), hipMemcpyDeviceToHost, s));
+      GC(hipStreamSynchronize(s));
+      bool still = false;
+      for (int k = 0; k < q; ++k) {
+        if (!active[k]) continue;
+        jdone[k] = j + 1;
+        iters[k] += 1;
+        if (e[k] / nb[k] < rtol || iters[k] >= maxit) active[k] = 0;
+        still = still || active[k];
+      }
+      GC(hipMemcpyAsync(act, active.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
+      if (!still) break;
+    }
+    GC(hipMemcpyAsync(jd, jdone.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
+    GC(launch_gmres_solve_small(q, m, jd, H, g, y, s));
+    GC(launch_basis_combine(q, n, jd, Zb, vs, y, u, s));
+    GC(launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, u, b, W, 1, s));
+    GT(norms(c, q, n, W, tmp, beta));
+  }
+  cleanup();
+#undef GC
+#undef GT
+  return HH_OK;
+}
+
+hh_status stationary(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit, const std::vector<double>& nb,
+                     std::vector<int>& iters, std::vector<double>& relres, std::vector<int>& conv) {
+  const long long n = c->lv[0].total;
+  const long long vs = (long long)q * n;
+  hipStream_t s = c->stream;
+  c128 *r = nullptr, *z = nullptr, *tmp = nullptr;
+  int* act = nullptr;
+  hh_status st = HH_OK;
+  auto cleanup = [&]() {
+    for (void* p : std::initializer_list<void*>{r, z, tmp, act}) dfree(c, p);
+  };
+  if ((st = dalloc(c, &r, (size_t)vs)) != HH_OK || (st = dalloc(c, &z, (size_t)vs)) != HH_OK ||
+      (st = dalloc(c, &tmp, (size_t)q)) != HH_OK || (st = dalloc(c, &act, (size_t)q)) != HH_OK) {
+    cleanup();
+    return st;
+  }
+  std::vector<double> rn(q);
+  std::vector<int> active(q);
+  hipError_t e;
+  if ((e = launch_fill_zero(u, vs * (long long)sizeof(c128), s)) != hipSuccess ||
+      (e = launch_copy(b, r, vs, s)) != hipSuccess) {
+    cleanup();
+    return device_fail(c, "stationary init", e);
+  }
+  while (true) {
+    if ((st = norms(c, q, n, r, tmp, rn)) != HH_OK) break;
+    bool any = false;
+    for (int k = 0; k < q; ++k) {
+      relres[k] = nb[k] > 0.0 ? rn[k] / nb[k] : 0.0;
+      conv[k] = relres[k] < rtol || nb[k] == 0.0;
+      active[k] = !conv[k] && iters[k] < maxit;
+      any = any || active[k];
+    }
+    if (!any) break;
+    if ((st = two_level(c, 0, q, r, z)) != HH_OK) break;
+    if ((e = hipMemcpyAsync(act, active.data(), q * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_add_masked(z, u, n, q, act, s)) != hipSuccess ||
+        (e = launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, u, b, r, 1, s)) != hipSuccess) {
+      cleanup();
+      return device_fail(c, "stationary step", e);
+    }
+    for (int k = 0; k < q; ++k) iters[k] += active[k];
+  }
+  cleanup();
+  return st;
+}
+
+}  // namespace
+
+extern "C" hh_status hh_solve(hh_ctx* c, int32_t nrhs, const void* f, const void* g, void* u, double rtol,
+                              int32_t maxit, hh_solve_info* info) {
+  HH_TRY(check_usable(c));
+  if (nrhs <= 0 || !f || !u || maxit < 0 || !(rtol >= 0.0)) return fail(c, HH_EINVAL, "bad arguments to hh_solve");
+  HH_TRY(check_built(c));
+  const int q = nrhs;
+  const long long n = c->lv[0].total;
+  HH_TRY(ensure_work(c, 0, q));
+  Level& R0 = c->lv[0];
+  const c128* b = reinterpret_cast<const c128*>(f);
+  if (g) {
+    // b = f + (boundary facets)/2^(dim-1) * g / h, built by the stencil kernel's rhs mode on E
+    HH_CHECK(launch_rhs_with_impedance(c->op, R0.d, q, b, reinterpret_cast<const c128*>(g), R0.E, c->stream));
+    b = R0.E;
+  }
+  std::vector<double> nb;
+  HH_TRY(ensure_partial(c, (size_t)q * multidot_nblocks(n)));
+  c128* tmp = nullptr;
+  HH_TRY(dalloc(c, &tmp, (size_t)q));
+  hh_status st = norms(c, q, n, b, tmp, nb);
+  dfree(c, tmp);
+  if (st != HH_OK) return st;
+  for (double v : nb)
+    if (!std::isfinite(v)) return fail(c, HH_EINVAL, "right-hand side holds NaN or Inf");
+  std::vector<int> iters(q, 0), conv(q, 0);
+  std::vector<double> relres(q, 0.0);
+  if (c->outer == HH_GMRES)
+    st = gmres(c, q, b, reinterpret_cast<c128*>(u), rtol, maxit, nb, iters, relres, conv);
+  else
+    st = stationary(c, q, b, reinterpret_cast<c128*>(u), rtol, maxit, nb, iters, relres, conv);
+  if (st != HH_OK) return st;
+  bool all = true;
+  for (int k = 0; k < q; ++k) {
+    if (info) {
+      info[k].iters = iters[k];
+      info[k].converged = conv[k];
+      info[k].rel_residual = relres[k];
+    }
+    all = all && conv[k];
+  }
+  if (!all) return fail(c, HH_ENOTCONV, "not converged within maxit");
+  return HH_OK;
+}
+
+extern "C" hh_status hh_get_coarse(hh_ctx* c, int32_t level, int32_t parent, int32_t* n_c, void* Ac_host,
+                                   double* sigma_host) {
+  HH_TRY(check_usable(c));
+  if (level < 0 || level >= c->L) return fail(c, HH_EINVAL, "level must be in 0..levels-1");
+  Level& P = c->lv[level];
+  Level& Ch = c->lv[level + 1];
+  if (!Ch.built) return fail(c, HH_ESTATE, "coarse space not built");
+  if (parent < 0 || parent >= P.nbox) return fail(c, HH_EINVAL, "parent out of range");
+  const ParentDev& pd = P.hp[parent];
+  if (n_c) *n_c = pd.n_c;
+  if (Ac_host && pd.n_c > 0) {
+    HH_CHECK(hipMemcpyAsync(Ac_host, P.Araw + pd.aoff, (size_t)pd.n_c * pd.n_c * sizeof(c128),
+                            hipMemcpyDeviceToHost, c->stream));
+    HH_TRY(sync(c));
+  }
+  if (sigma_host) {
+    size_t o = 0;
+    for (int ch : c->geo.levels[level][parent].children) {
+      const int sw = Ch.hb[ch].s;
+      for (int t = 0; t < sw; ++t) sigma_host[o++] = Ch.sigma[(size_t)ch * Ch.smax + t];
+    }
+  }
+  return HH_OK;
+}
+
+extern "C" hh_status hh_get_basis(hh_ctx* c, int32_t level, int32_t box, int32_t* n_own, int32_t* r_i,
+                                  void* C_host) {
+  HH_TRY(check_usable(c));
+  if (level < 1 || level > c->L) return fail(c, HH_EINVAL, "level must be in 1..levels");
+  Level& Lv = c->lv[level];
+  if (!Lv.built) return fail(c, HH_ESTATE, "coarse space not built");
+  if (box < 0 || box >= Lv.nbox) return fail(c, HH_EINVAL, "box out of range");
+  const BoxDev& b = Lv.hb[box];
+  if (n_own) *n_own = b.n_own;
+  if (r_i) *r_i = b.r;
+  if (C_host && b.r > 0) {
+    HH_CHECK(hipMemcpyAsync(C_host, Lv.C + b.coff, (size_t)b.r * b.n_own * sizeof(c128), hipMemcpyDeviceToHost,
+                            c->stream));
+    HH_TRY(sync(c));
+  }
+  return HH_OK;
+}

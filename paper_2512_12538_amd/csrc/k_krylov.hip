@@ -1,0 +1,202 @@
+// Device side of the outer loops: batched inner products with a fixed
+// reduction tree (the split into blocks depends on the vector length only, so
+// a right-hand side gets bit-identical results alone and inside any batch),
+// the Gram-Schmidt updates, and the per-right-hand-side GMRES bookkeeping
+// (Givens rotations of the Hessenberg column, the small triangular solve).
+#include "kernels.h"
+
+namespace {
+
+constexpr int TB = 256;
+constexpr int CHUNK = 4096;  // nodes per partial sum
+constexpr int MAXNB = 512;
+
+inline int nblocks(long long n) {
+  long long nb = (n + CHUNK - 1) / CHUNK;
+  if (nb < 1) nb = 1;
+  if (nb > MAXNB) nb = MAXNB;
+  return (int)nb;
+}
+
+// partial[(k*q + b)*NB + blk] = sum over the block's chunk of conj(V_k[b]) W[b]
+__global__ void __launch_bounds__(TB) k_dot_partial(int q, long long n, int NB, const c128* __restrict__ V,
+                                                    long long vstride, const c128* __restrict__ W,
+                                                    c128* __restrict__ partial) {
+  const int blk = blockIdx.x, k = blockIdx.y, b = blockIdx.z;
+  const long long per = (n + NB - 1) / NB;
+  const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
+  const c128* v = V + k * vstride + (long long)b * n;
+  const c128* w = W + (long long)b * n;
+  double2 acc = mk(0.0, 0.0);
+  for (long long i = lo + threadIdx.x; i < hi; i += TB) acc = cfmac(v[i], w[i], acc);
+  __shared__ double sx[TB], sy[TB];
+  sx[threadIdx.x] = acc.x;
+  sy[threadIdx.x] = acc.y;
+  __syncthreads();
+  for (int st = TB / 2; st > 0; st >>= 1) {
+    if (threadIdx.x < st) {
+      sx[threadIdx.x] += sx[threadIdx.x + st];
+      sy[threadIdx.x] += sy[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[((long long)k * q + b) * NB + blk] = mk(sx[0], sy[0]);
+}
+
+__global__ void k_dot_final(int nkq, int NB, const c128* __restrict__ partial, c128* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nkq) return;
+  double2 acc = mk(0.0, 0.0);
+  for (int blk = 0; blk < NB; ++blk) acc = cadd(acc, partial[(long long)t * NB + blk]);
+  out[t] = acc;
+}
+
+__global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n, const c128* __restrict__ V,
+                                                     long long vstride, const c128* __restrict__ h,
+                                                     c128* __restrict__ W) {
+  const int b = blockIdx.y;
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    double2 w = W[(long long)b * n + i];
+    for (int k = 0; k < nk; ++k) w = csub(w, cmul(V[k * vstride + (long long)b * n + i], h[k * q + b]));
+    W[(long long)b * n + i] = w;
+  }
+}
+
+__global__ void __launch_bounds__(TB) k_normalize(int q, long long n, const c128* __restrict__ nrm2,
+                                                  const c128* __restrict__ x, c128* __restrict__ y,
+                                                  double* __restrict__ nrm) {
+  const int b = blockIdx.y;
+  const double nv = sqrt(fmax(nrm2[b].x, 0.0));
+  const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && nrm) nrm[b] = nv;
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB)
+    y[(long long)b * n + i] = cscale(x[(long long)b * n + i], inv);
+}
+
+// One Arnoldi column per right-hand side: H[:, j] = h1 + h2, H[j+1, j] = ||w||,
+// previous rotations, a new rotation zeroing H[j+1, j], and the update of g.
+// Layout per rhs b: H[b][(m+1)*col + row], cs/sn[b][m], g[b][m+1].
+__global__ void k_gmres_step(int q, int j, int m, c128* __restrict__ H, const c128* __restrict__ h1,
+                             const c128* __restrict__ h2, const double* __restrict__ hnext,
+                             c128* __restrict__ cs, c128* __restrict__ sn, c128* __restrict__ g,
+                             double* __restrict__ est, const int* __restrict__ active) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= q) return;
+  if (active && !active[b]) return;
+  c128* Hb = H + (long long)b * (m + 1) * m;
+  c128* cb = cs + (long long)b * m;
+  c128* sb = sn + (long long)b * m;
+  c128* gb = g + (long long)b * (m + 1);
+  c128* col = Hb + (long long)(m + 1) * j;
+  for (int t = 0; t <= j; ++t) col[t] = cadd(h1[t * q + b], h2[t * q + b]);
+  col[j + 1] = mk(hnext[b], 0.0);
+  for (int t = 0; t < j; ++t) {
+    const double2 a = col[t], bb = col[t + 1];
+    col[t] = cadd(cmulc(cb[t], a), cmulc(sb[t], bb));
+    col[t + 1] = csub(cmul(cb[t], bb), cmul(sb[t], a));
+  }
+  const double2 a = col[j], bb = col[j + 1];
+  const double den = sqrt(cabs2(a) + cabs2(bb));
+  double2 c, s;
+  if (den == 0.0) {
+    c = mk(1.0, 0.0);
+    s = mk(0.0, 0.0);
+  } else {
+    c = cscale(a, 1.0 / den);
+    s = cscale(bb, 1.0 / den);
+  }
+  cb[j] = c;
+  sb[j] = s;
+  col[j] = mk(den, 0.0);
+  col[j + 1] = mk(0.0, 0.0);
+  const double2 gj = gb[j];
+  gb[j + 1] = mk(-(s.x * gj.x - s.y * gj.y), -(s.x * gj.y + s.y * gj.x));
+  gb[j] = cmulc(c, gj);
+  est[b] = sqrt(cabs2(gb[j + 1]));
+}
+
+// y[k*q + b] for k < jdone[b]: back substitution with the rotated (upper
+// triangular) Hessenberg matrix.
+__global__ void k_gmres_solve_small(int q, int m, const int* __restrict__ jdone, const c128* __restrict__ H,
+                                    const c128* __restrict__ g, c128* __restrict__ y) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= q) return;
+  const int jd = jdone[b];
+  const c128* Hb = H + (long long)b * (m + 1) * m;
+  const c128* gb = g + (long long)b * (m + 1);
+  for (int k = jd - 1; k >= 0; --k) {
+    double2 s = gb[k];
+    for (int t = k + 1; t < jd; ++t) s = csub(s, cmul(Hb[(long long)(m + 1) * t + k], y[t * q + b]));
+    y[k * q + b] = cdiv(s, Hb[(long long)(m + 1) * k + k]);
+  }
+  for (int k = jd; k < m; ++k) y[k * q + b] = mk(0.0, 0.0);
+}
+
+// u[b] += sum_{k < jdone[b]} Z_k[b] y[k][b]
+__global__ void __launch_bounds__(TB) k_basis_combine(int q, long long n, const int* __restrict__ jdone,
+                                                      const c128* __restrict__ Z, long long zstride,
+                                                      const c128* __restrict__ y, c128* __restrict__ u) {
+  const int b = blockIdx.y;
+  const int jd = jdone[b];
+  if (jd == 0) return;
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+    double2 acc = u[(long long)b * n + i];
+    for (int k = 0; k < jd; ++k) acc = cfma(Z[k * zstride + (long long)b * n + i], y[k * q + b], acc);
+    u[(long long)b * n + i] = acc;
+  }
+}
+
+inline int gx(long long n, int cap) {
+  long long g = (n + TB - 1) / TB;
+  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+int multidot_nblocks(long long n) { return nblocks(n); }
+
+hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long vstride, const c128* W,
+                           c128* partial, c128* out, hipStream_t s) {
+  if (nk <= 0 || q <= 0) return hipSuccess;
+  const int NB = nblocks(n);
+  hipLaunchKernelGGL(k_dot_partial, dim3(NB, nk, q), dim3(TB), 0, s, q, n, NB, V, vstride, W, partial);
+  const int nkq = nk * q;
+  hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, NB, partial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h,
+                               c128* W, hipStream_t s) {
+  if (nk <= 0 || q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_basis_update, dim3(gx(n, 1024), q), dim3(TB), 0, s, nk, q, n, V, vstride, h, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(int q, long long n, const c128* nrm2, const c128* x, c128* y, double* nrm,
+                            hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normalize, dim3(gx(n, 1024), q), dim3(TB), 0, s, q, n, nrm2, x, y, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmres_step(int q, int j, int m, c128* H, const c128* h1, const c128* h2, const double* hnext,
+                             c128* cs, c128* sn, c128* g, double* est, const int* active, hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gmres_step, dim3((q + 63) / 64), dim3(64), 0, s, q, j, m, H, h1, h2, hnext, cs, sn, g, est,
+                     active);
+  return hipGetLastError();
+}
+
+hipError_t launch_gmres_solve_small(int q, int m, const int* jdone, const c128* H, const c128* g, c128* y,
+                                    hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gmres_solve_small, dim3((q + 63) / 64), dim3(64), 0, s, q, m, jdone, H, g, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_basis_combine(int q, long long n, const int* jdone, const c128* Z, long long zstride,
+                                const c128* y, c128* u, hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_basis_combine, dim3(gx(n, 1024), q), dim3(TB), 0, s, q, n, jdone, Z, zstride, y, u);
+  return hipGetLastError();
+}

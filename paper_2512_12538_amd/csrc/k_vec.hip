@@ -1,0 +1,194 @@
+// Stencil application, restriction/prolongation between levels, and vector
+// utilities.  All of these are bandwidth-bound streams over level buffers:
+// one thread per node, consecutive threads on consecutive q (contiguous in
+// memory), the grid's y dimension enumerating (box, column).
+#include "kernels.h"
+
+namespace {
+
+constexpr int TB = 256;
+
+// One 5-point row of the cell-assembled box matrix applied to a local vector.
+__device__ __forceinline__ double2 apply_row(const OpDev& op, const BoxDev& B, const c128* __restrict__ x,
+                                             int a, int c) {
+  const int p = B.p0 + a, q = B.q0 + c;
+  const int l = a * B.ny + c;
+  double2 acc = cmul(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 0, 0), x[l]);
+  if (a > 0) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, -1, 0), x[l - B.ny], acc);
+  if (a < B.nx - 1) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 1, 0), x[l + B.ny], acc);
+  if (op.dim == 2) {
+    if (c > 0) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 0, -1), x[l - 1], acc);
+    if (c < B.ny - 1) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 0, 1), x[l + 1], acc);
+  }
+  return acc;
+}
+
+__global__ void __launch_bounds__(TB) k_apply_box(OpDev op, const BoxDev* __restrict__ boxes, int q,
+                                                  const c128* __restrict__ x, const c128* __restrict__ b,
+                                                  c128* __restrict__ y, int mode) {
+  const int bc = blockIdx.y;
+  const int box = bc / q, col = bc % q;
+  const BoxDev B = boxes[box];
+  const long long base = B.voff * q + (long long)col * B.n;
+  for (int l = blockIdx.x * TB + threadIdx.x; l < B.n; l += gridDim.x * TB) {
+    const int a = l / B.ny, c = l - a * B.ny;
+    double2 v = apply_row(op, B, x + base, a, c);
+    if (mode == 1) v = csub(b[base + l], v);
+    y[base + l] = v;
+  }
+}
+
+__global__ void __launch_bounds__(TB) k_gather_children(const BoxDev* __restrict__ child,
+                                                        const BoxDev* __restrict__ par, int q,
+                                                        const c128* __restrict__ pbuf, c128* __restrict__ cbuf) {
+  const int bc = blockIdx.y;
+  const int box = bc / q, col = bc % q;
+  const BoxDev C = child[box];
+  const BoxDev P = par[C.parent];
+  const long long cb = C.voff * q + (long long)col * C.n;
+  const long long pb = P.voff * q + (long long)col * P.n;
+  const int da = C.p0 - P.p0, dc = C.q0 - P.q0;
+  for (int l = blockIdx.x * TB + threadIdx.x; l < C.n; l += gridDim.x * TB) {
+    const int a = l / C.ny, c = l - a * C.ny;
+    cbuf[cb + l] = pbuf[pb + (long long)(a + da) * P.ny + (c + dc)];
+  }
+}
+
+__global__ void __launch_bounds__(TB) k_scatter_owned(const BoxDev* __restrict__ child,
+                                                      const BoxDev* __restrict__ par, int q,
+                                                      const c128* __restrict__ cbuf, c128* __restrict__ pbuf) {
+  const int bc = blockIdx.y;
+  const int box = bc / q, col = bc % q;
+  const BoxDev C = child[box];
+  const BoxDev P = par[C.parent];
+  const long long cb = C.voff * q + (long long)col * C.n;
+  const long long pb = P.voff * q + (long long)col * P.n;
+  for (int t = blockIdx.x * TB + threadIdx.x; t < C.n_own; t += gridDim.x * TB) {
+    const int oa = t / C.own_ny, oc = t - oa * C.own_ny;
+    const int p = C.op0 + oa, qq = C.oq0 + oc;
+    pbuf[pb + (long long)(p - P.p0) * P.ny + (qq - P.q0)] = cbuf[cb + (long long)(p - C.p0) * C.ny + (qq - C.q0)];
+  }
+}
+
+__global__ void k_fill_zero(uint4* __restrict__ p, long long n16) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n16; i += (long long)gridDim.x * TB)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+__global__ void k_fill_zero_bytes(unsigned char* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) p[i] = 0;
+}
+
+__global__ void k_conj(c128* __restrict__ x, long long n) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB)
+    x[i] = cconj(x[i]);
+}
+
+__global__ void k_copy(const c128* __restrict__ x, c128* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) y[i] = x[i];
+}
+
+__global__ void k_add_masked(const c128* __restrict__ x, c128* __restrict__ y, long long n,
+                             const int* __restrict__ active) {
+  const int col = blockIdx.y;
+  if (active && !active[col]) return;
+  const long long base = (long long)col * n;
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB)
+    y[base + i] = cadd(y[base + i], x[base + i]);
+}
+
+__global__ void k_f64_to_f32(const c128* __restrict__ x, c64* __restrict__ y, long long n) {
+  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB)
+    y[i] = to_c64(x[i]);
+}
+
+__global__ void __launch_bounds__(TB) k_rhs_g(OpDev op, const BoxDev* __restrict__ root, int q,
+                                              const c128* __restrict__ f, const c128* __restrict__ g,
+                                              c128* __restrict__ out) {
+  const BoxDev B = root[0];
+  const int col = blockIdx.y;
+  const long long base = (long long)col * B.n;
+  for (int l = blockIdx.x * TB + threadIdx.x; l < B.n; l += gridDim.x * TB) {
+    const int a = l / B.ny, c = l - a * B.ny;
+    const int p = B.p0 + a, qq = B.q0 + c;
+    const double cx = (double)((p > B.p0) + (p < B.p1));
+    const double cy = op.dim == 2 ? (double)((qq > B.q0) + (qq < B.q1)) : 2.0;
+    double nb = (p == B.p0 || p == B.p1) ? cy : 0.0;
+    if (op.dim == 2 && (qq == B.q0 || qq == B.q1)) nb += cx;
+    out[base + l] = cadd(f[base + l], cscale(g[base + l], 0.5 * nb / op.h));
+  }
+}
+
+inline int grid_for(long long n, int cap = 4096) {
+  long long g = (n + TB - 1) / TB;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_apply_box(const OpDev& op, const BoxDev* boxes, int nbox, int max_n, int q,
+                            const c128* x, const c128* b, c128* y, int mode, hipStream_t s) {
+  if (nbox <= 0 || q <= 0) return hipSuccess;
+  dim3 grid(grid_for(max_n, 1024), nbox * q);
+  hipLaunchKernelGGL(k_apply_box, grid, dim3(TB), 0, s, op, boxes, q, x, b, y, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_children(const BoxDev* child, int nchild, int max_n, const BoxDev* par, int q,
+                                  const c128* pbuf, c128* cbuf, hipStream_t s) {
+  if (nchild <= 0 || q <= 0) return hipSuccess;
+  dim3 grid(grid_for(max_n, 1024), nchild * q);
+  hipLaunchKernelGGL(k_gather_children, grid, dim3(TB), 0, s, child, par, q, pbuf, cbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_scatter_owned(const BoxDev* child, int nchild, int max_own, const BoxDev* par, int q,
+                                const c128* cbuf, c128* pbuf, hipStream_t s) {
+  if (nchild <= 0 || q <= 0) return hipSuccess;
+  dim3 grid(grid_for(max_own, 1024), nchild * q);
+  hipLaunchKernelGGL(k_scatter_owned, grid, dim3(TB), 0, s, child, par, q, cbuf, pbuf);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t s) {
+  if (bytes <= 0) return hipSuccess;
+  if ((reinterpret_cast<uintptr_t>(p) & 15) == 0 && (bytes & 15) == 0) {
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(bytes / 16)), dim3(TB), 0, s, (uint4*)p, bytes / 16);
+  } else {
+    hipLaunchKernelGGL(k_fill_zero_bytes, dim3(grid_for(bytes)), dim3(TB), 0, s, (unsigned char*)p, bytes);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_conj_inplace(c128* x, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_conj, dim3(grid_for(n)), dim3(TB), 0, s, x, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const c128* x, c128* y, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(TB), 0, s, x, y, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_masked(const c128* x, c128* y, long long n, int q, const int* active, hipStream_t s) {
+  if (n <= 0 || q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_masked, dim3(grid_for(n, 1024), q), dim3(TB), 0, s, x, y, n, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_rhs_with_impedance(const OpDev& op, const BoxDev* root, int q, const c128* f, const c128* g,
+                                     c128* out, hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rhs_g, dim3(1024, q), dim3(TB), 0, s, op, root, q, f, g, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const c128* x, c64* y, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(n)), dim3(TB), 0, s, x, y, n);
+  return hipGetLastError();
+}

@@ -1,0 +1,98 @@
+// Launch wrappers of the HIP kernels.  Every wrapper enqueues on the given
+// stream and returns hipGetLastError().  Level buffers hold, for each box of a
+// level, q columns of the box's local vector: box i, column c, local node x at
+// index voff_i * q + c * n_i + x.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+// ---------------------------------------------------------------- vectors / stencil (k_vec.hip)
+// y = A_box x (mode 0) or y = b - A_box x (mode 1) for every box and column of a level buffer.
+hipError_t launch_apply_box(const OpDev& op, const BoxDev* boxes, int nbox, int max_n, int q,
+                            const c128* x, const c128* b, c128* y, int mode, hipStream_t s);
+// child[c][col][x] = parent[parent(c)][col][R_c x]
+hipError_t launch_gather_children(const BoxDev* child, int nchild, int max_n, const BoxDev* par, int q,
+                                  const c128* pbuf, c128* cbuf, hipStream_t s);
+// parent[parent(c)][col][x] = child[c][col][x] for x owned by c
+hipError_t launch_scatter_owned(const BoxDev* child, int nchild, int max_own, const BoxDev* par, int q,
+                                const c128* cbuf, c128* pbuf, hipStream_t s);
+hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t s);
+hipError_t launch_conj_inplace(c128* x, long long n, hipStream_t s);
+hipError_t launch_copy(const c128* x, c128* y, long long n, hipStream_t s);
+// y[col] += x[col] for the columns with active[col] != 0 (all if active is null); columns of length n
+hipError_t launch_add_masked(const c128* x, c128* y, long long n, int q, const int* active, hipStream_t s);
+hipError_t launch_f64_to_f32(const c128* x, c64* y, long long n, hipStream_t s);
+// out = f + (boundary edges at the node)/2 * g / h on the whole-domain box (1D: g/h at the ends)
+hipError_t launch_rhs_with_impedance(const OpDev& op, const BoxDev* root, int q, const c128* f, const c128* g,
+                                     c128* out, hipStream_t s);
+
+// ---------------------------------------------------------------- leaf solves (k_leaf.hip)
+// Block-tridiagonal factorisation of every leaf box: G_j = S_j^{-1} per grid line (FP64).
+hipError_t launch_leaf_factor(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, c128* G,
+                              int* info, hipStream_t s);
+template <typename T>
+hipError_t launch_leaf_solve(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, int q,
+                             const typename cvec<T>::type* G, const c128* rhs, c128* x, hipStream_t s);
+
+// ---------------------------------------------------------------- interface map / rSVD (k_rsvd.hip)
+// buf[box][c][iface[t]] = vals[voff[box] + c*m_in + t] for c < (use_r ? r : s); buf pre-zeroed
+hipError_t launch_iface_scatter(const BoxDev* boxes, int nbox, int q, const int* if_idx, const long long* voff,
+                                const c128* vals, int use_r, c128* buf, hipStream_t s);
+hipError_t launch_iface_gather(const BoxDev* boxes, int nbox, int q, const int* if_idx, const long long* voff,
+                               const c128* buf, c128* vals, int use_r, hipStream_t s);
+// Y[yoff[box] + c*tr_cnt + row] = (A~_j R_j P_i X)[x_row]
+hipError_t launch_trace(const OpDev& op, const BoxDev* boxes, int nbox, int q, const int2* rows,
+                        const long long* yoff, const c128* X, c128* Y, hipStream_t s);
+// H[box][c][y] = sum_rows conj(A~_j[x, y]) Q[row][c]; H pre-zeroed
+hipError_t launch_trace_adjoint(const OpDev& op, const BoxDev* boxes, int nbox, int q, const int2* rows,
+                                const int* seg_ptr, const int* seg_y, const int4* adj, const long long* yoff,
+                                const c128* Qm, c128* H, hipStream_t s);
+// Batched Householder QR: A[b] (m_b x n_b col-major) -> explicit Q in place, R (n_b x n_b); n_b <= 128
+hipError_t launch_qr(int nprob, const int* m, const int* n, const long long* aoff, c128* A, const long long* roff,
+                     c128* R, c128* work, hipStream_t s);
+// One-sided Jacobi SVD of R[b] (n_b x n_b, n_b <= 128): U sorted by decreasing singular value, sigma
+hipError_t launch_jacobi_svd(int nprob, const int* n, const long long* roff, c128* R, const long long* uoff,
+                             c128* U, double* sigma, const long long* soff, hipStream_t s);
+// V[b] (m_b x r_b) = Q[b] (m_b x n_b) * U[b][:, :r_b]
+hipError_t launch_small_gemm(int nprob, int max_mr, const int* m, const int* n, const int* r, const long long* qoff,
+                             const c128* Q, const long long* uoff, const c128* U, const long long* voff, c128* V,
+                             hipStream_t s);
+// C[box] (r x n_own) = buf[box][c][owned nodes]
+hipError_t launch_extract_owned(const BoxDev* boxes, int nbox, int max_own, int q, const c128* buf, c128* C,
+                                hipStream_t s);
+
+// ---------------------------------------------------------------- coarse space (k_coarse.hip)
+hipError_t launch_galerkin_ac(const OpDev& op, const BoxDev* boxes, int nbox, const BoxDev* par, const int4* dil,
+                              int max_dil, int rmax, const c128* C, c128* AC, hipStream_t s);
+hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, const int4* pairs, int npairs,
+                                  int rmax, const int4* dil, const c128* C, const c128* AC, c128* Ac,
+                                  hipStream_t s);
+hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, int* info,
+                             hipStream_t s);
+hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const BoxDev* par, const ParentDev* pd,
+                                  int rmax, int q, const c128* C, const c128* t, c128* cvec, hipStream_t s);
+hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, const c128* Ainv,
+                              const c128* cvec, c128* y, hipStream_t s);
+hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
+                                 const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
+                                 hipStream_t s);
+
+// ---------------------------------------------------------------- Krylov (k_krylov.hip)
+int multidot_nblocks(long long n);
+// out[k*q + b] = sum_x conj(V_k[b][x]) W[b][x], k < nk (V_k at V + k*vstride); partial: nk*q*NB entries
+hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long vstride, const c128* W,
+                           c128* partial, c128* out, hipStream_t s);
+// W[b] -= sum_k V_k[b] h[k*q + b]
+hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h,
+                               c128* W, hipStream_t s);
+// y[b] = x[b] / sqrt(re nrm2[b]) (zero if the norm is zero); nrm[b] = the norm
+hipError_t launch_normalize(int q, long long n, const c128* nrm2, const c128* x, c128* y, double* nrm,
+                            hipStream_t s);
+hipError_t launch_gmres_step(int q, int j, int m, c128* H, const c128* h1, const c128* h2, const double* hnext,
+                             c128* cs, c128* sn, c128* g, double* est, const int* active, hipStream_t s);
+hipError_t launch_gmres_solve_small(int q, int m, const int* jdone, const c128* H, const c128* g, c128* y,
+                                    hipStream_t s);
+hipError_t launch_basis_combine(int q, long long n, const int* jdone, const c128* Z, long long zstride,
+                                const c128* y, c128* u, hipStream_t s);
