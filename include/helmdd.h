@@ -81,7 +81,7 @@ typedef struct {
 typedef struct {
   int32_t precision;     /* hh_precision: HH_MIXED keeps the leaf factors in complex64 */
   int32_t outer;         /* hh_outer used by hh_solve */
-  int32_t gmres_restart; /* restart length (default 50 when <= 0) */
+  int32_t gmres_restart; /* restart length (default 50 when <= 0, at most 120) */
   void* stream;          /* hipStream_t, or null */
 } hh_options;
 

@@ -89,6 +89,8 @@ struct hh_ctx {
   std::vector<DevBuf> scratch;
   c128* d_partial = nullptr;
   size_t partial_cap = 0;
+  int* poll = nullptr;          // pinned host words polled by the outer loop
+  hipEvent_t poll_ev[2] = {nullptr, nullptr};
   std::vector<void*> allocs;
 };
 
@@ -180,6 +182,20 @@ hh_status ensure_work(hh_ctx* c, int lo, int q) {
     }
     L.qcap = q;
   }
+  return HH_OK;
+}
+
+hh_status ensure_poll(hh_ctx* c) {
+  if (c->poll) return HH_OK;
+  void* p = nullptr;
+  if (hipHostMalloc(&p, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, HH_ENOMEM, "hipHostMalloc failed");
+  }
+  c->poll = reinterpret_cast<int*>(p);
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&c->poll_ev[i], hipEventDisableTiming) != hipSuccess)
+      return device_fail(c, "hipEventCreateWithFlags", hipGetLastError());
   return HH_OK;
 }
 
@@ -281,6 +297,9 @@ const char* hh_last_error(const hh_ctx* c) { return c ? c->err.c_str() : "null c
 hh_status hh_destroy(hh_ctx* c) {
   if (!c) return HH_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int i = 0; i < 2; ++i)
+    if (c->poll_ev[i]) (void)hipEventDestroy(c->poll_ev[i]);
+  if (c->poll) (void)hipHostFree(c->poll);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
   delete c;
@@ -306,7 +325,7 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
     c->stream = reinterpret_cast<hipStream_t>(o->stream);
     c->precision = o->precision == HH_MIXED ? HH_MIXED : HH_FP64;
     c->outer = o->outer == HH_STATIONARY ? HH_STATIONARY : HH_GMRES;
-    c->restart = o->gmres_restart > 0 ? o->gmres_restart : 50;
+    c->restart = o->gmres_restart > 0 ? std::min(o->gmres_restart, 120) : 50;
   }
   std::string msg = build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, c->geo);
   if (!msg.empty()) {
@@ -383,7 +402,9 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
   c->g_total = goff;
   for (int l = 0; l <= c->L; ++l)
     if ((st = push_boxes(c, c->lv[l])) != HH_OK) return bail(st);
-  if ((st = dalloc(c, &c->G, (size_t)goff)) != HH_OK) return bail(st);
+  // tail padding: the pipelined solve reads (masked) up to K*R rows past a line's end
+  const long long gpad = 256LL * 256LL;
+  if ((st = dalloc(c, &c->G, (size_t)(goff + gpad))) != HH_OK) return bail(st);
   if ((st = dalloc(c, &c->d_info, (size_t)std::max(leaf.nbox, 4096))) != HH_OK) return bail(st);
   if (launch_leaf_factor(c->op, leaf.d, leaf.nbox, leaf.max_ny, c->G, c->d_info, c->stream) != hipSuccess)
     return bail(device_fail(c, "leaf factor", hipGetLastError()));
@@ -399,7 +420,7 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
       return HH_ESINGULAR;
     }
   if (c->precision == HH_MIXED) {
-    if ((st = dalloc(c, &c->G32, (size_t)goff)) != HH_OK) return bail(st);
+    if ((st = dalloc(c, &c->G32, (size_t)(goff + gpad))) != HH_OK) return bail(st);
     if (launch_f64_to_f32(c->G, c->G32, goff, c->stream) != hipSuccess)
       return bail(device_fail(c, "convert", hipGetLastError()));
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(device_fail(c, "sync", hipGetLastError()));
@@ -620,7 +641,7 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
     if ((st = upload(c, &d_bhoff, bhoff)) != HH_OK) break;
     if ((st = upload(c, &d_voff, voff)) != HH_OK) break;
     if ((st = upload(c, &d_omoff, omoff)) != HH_OK) break;
-    const size_t ysz = std::max<long long>(yt, bht);
+    const size_t ysz = std::max<long long>(std::max<long long>(yt, bht), (long long)P.nbox * max_nc);
     if ((st = dalloc(c, &Y, ysz)) != HH_OK) break;
     if ((st = dalloc(c, &Wk, ysz)) != HH_OK) break;
     if ((st = dalloc(c, &Rs, (size_t)Lv.nbox * smax * smax)) != HH_OK) break;
@@ -682,7 +703,7 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   BC(launch_fill_zero(P.Ainv, nc2 * sizeof(c128), s));
   BC(launch_galerkin_blocks(Lv.d, P.dp, Lv.d_pairs, Lv.npairs, rmax, Lv.d_dil, Lv.C, Lv.AC, P.Ainv, s));
   BC(launch_copy(P.Ainv, P.Araw, nc2, s));
-  BC(launch_gj_inverse(P.dp, P.nbox, max_nc, P.Ainv, P.d_piv, c->d_info, s));
+  BC(launch_gj_inverse(P.dp, P.nbox, max_nc, P.Ainv, P.d_piv, Wk, c->d_info, s));
   std::vector<int> info(P.nbox);
   BC(hipMemcpyAsync(info.data(), c->d_info, P.nbox * sizeof(int), hipMemcpyDeviceToHost, s));
   BC(hipMemcpyAsync(Lv.sigma.data(), d_sig, (size_t)Lv.nbox * smax * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -726,10 +747,10 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
   hipStream_t s = c->stream;
   c128 *Vb = nullptr, *Zb = nullptr, *W = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   c128 *h1 = nullptr, *h2 = nullptr, *tmp = nullptr, *y = nullptr;
-  double *hn = nullptr, *est = nullptr;
-  int *act = nullptr, *jd = nullptr;
+  double *hn = nullptr, *est = nullptr, *thr = nullptr;
+  int *state = nullptr, *any = nullptr;
   auto cleanup = [&]() {
-    for (void* p : std::initializer_list<void*>{Vb, Zb, W, H, cs, sn, g, h1, h2, tmp, y, hn, est, act, jd})
+    for (void* p : std::initializer_list<void*>{Vb, Zb, W, H, cs, sn, g, h1, h2, tmp, y, hn, est, thr, state, any})
       dfree(c, p);
   };
   hh_status st = HH_OK;
@@ -747,9 +768,11 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     if ((st = dalloc(c, &y, (size_t)q * m)) != HH_OK) break;
     if ((st = dalloc(c, &hn, (size_t)q)) != HH_OK) break;
     if ((st = dalloc(c, &est, (size_t)q)) != HH_OK) break;
-    if ((st = dalloc(c, &act, (size_t)q)) != HH_OK) break;
-    if ((st = dalloc(c, &jd, (size_t)q)) != HH_OK) break;
+    if ((st = dalloc(c, &thr, (size_t)q)) != HH_OK) break;
+    if ((st = dalloc(c, &state, (size_t)3 * q)) != HH_OK) break;
+    if ((st = dalloc(c, &any, (size_t)2)) != HH_OK) break;
     if ((st = ensure_partial(c, (size_t)(m + 1) * q * multidot_nblocks(n))) != HH_OK) break;
+    if ((st = ensure_poll(c)) != HH_OK) break;
   } while (false);
   if (st != HH_OK) {
     cleanup();
@@ -772,59 +795,57 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     }                         \
   } while (0)
   const long long vs = (long long)q * n;
-  std::vector<double> beta(q);
-  std::vector<int> active(q), jdone(q);
+  std::vector<double> beta(q), th(q);
+  std::vector<int> hstate(3 * q);
+  for (int k = 0; k < q; ++k) th[k] = rtol * nb[k];
+  GC(hipMemcpyAsync(thr, th.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
   // u = 0, r = b
   GC(launch_fill_zero(u, vs * (long long)sizeof(c128), s));
   GC(launch_copy(b, W, vs, s));
   GT(norms(c, q, n, W, tmp, beta));
+  int* poll = c->poll;
   while (true) {
-    bool any = false;
+    bool any_active = false;
     for (int k = 0; k < q; ++k) {
       relres[k] = nb[k] > 0.0 ? beta[k] / nb[k] : 0.0;
       conv[k] = relres[k] < rtol || nb[k] == 0.0;
-      active[k] = !conv[k] && iters[k] < maxit;
-      any = any || active[k];
-      jdone[k] = 0;
+      hstate[k] = !conv[k] && iters[k] < maxit;
+      hstate[q + k] = 0;
+      hstate[2 * q + k] = iters[k];
+      any_active = any_active || hstate[k];
     }
-    if (!any) break;
-    // V_0 = r / beta; g = beta e_1
-    GC(launch_multidot(1, q, n, W, 0, W, c->d_partial, tmp, s));
+    if (!any_active) break;
+    // V_0 = r / beta (tmp holds ||r||^2 from norms()); g = beta e_1
     GC(launch_normalize(q, n, tmp, W, Vb, nullptr, s));
     std::vector<c128> g0((size_t)q * (m + 1), make_double2(0.0, 0.0));
     for (int k = 0; k < q; ++k) g0[(size_t)k * (m + 1)] = make_double2(beta[k], 0.0);
     GC(hipMemcpyAsync(g, g0.data(), g0.size() * sizeof(c128), hipMemcpyHostToDevice, s));
-    GC(hipMemcpyAsync(act, active.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
-    int j = 0;
-    for (; j < m; ++j) {
+    GC(hipMemcpyAsync(state, hstate.data(), 3 * q * sizeof(int), hipMemcpyHostToDevice, s));
+    for (int j = 0; j < m; ++j) {
       const c128* vj = Vb + j * vs;
       c128* zj = Zb + j * vs;
       GT(two_level(c, 0, q, vj, zj));
       GC(launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, zj, nullptr, W, 0, s));
+      // classical Gram-Schmidt twice; the second update also gives ||w||^2
       GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h1, s));
-      GC(launch_basis_update(j + 1, q, n, Vb, vs, h1, W, s));
+      GC(launch_basis_update(j + 1, q, n, Vb, vs, h1, W, nullptr, nullptr, s));
       GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h2, s));
-      GC(launch_basis_update(j + 1, q, n, Vb, vs, h2, W, s));
-      GC(launch_multidot(1, q, n, W, 0, W, c->d_partial, tmp, s));
+      GC(launch_basis_update(j + 1, q, n, Vb, vs, h2, W, c->d_partial, tmp, s));
       GC(launch_normalize(q, n, tmp, W, Vb + (j + 1) * vs, hn, s));
-      GC(launch_gmres_step(q, j, m, H, h1, h2, hn, cs, sn, g, est, act, s));
-      std::vector<double> e(q);
-      GC(hipMemcpyAsync(e.data(), est, q * sizeof(double), hipMemcpyDeviceToHost, s));
-      GC(hipStreamSynchronize(s));
-      bool still = false;
-      for (int k = 0; k < q; ++k) {
-        if (!active[k]) continue;
-        jdone[k] = j + 1;
-        iters[k] += 1;
-        if (e[k] / nb[k] < rtol || iters[k] >= maxit) active[k] = 0;
-        still = still || active[k];
+      GC(launch_gmres_step(q, j, m, H, h1, h2, hn, cs, sn, g, est, state, thr, maxit, any, s));
+      // poll the active count one step late so the stream never drains
+      GC(hipMemcpyAsync(poll + (j & 1), any, sizeof(int), hipMemcpyDeviceToHost, s));
+      GC(hipEventRecord(c->poll_ev[j & 1], s));
+      if (j > 0) {
+        GC(hipEventSynchronize(c->poll_ev[(j - 1) & 1]));
+        if (poll[(j - 1) & 1] == 0) break;
       }
-      GC(hipMemcpyAsync(act, active.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
-      if (!still) break;
     }
-    GC(hipMemcpyAsync(jd, jdone.data(), q * sizeof(int), hipMemcpyHostToDevice, s));
-    GC(launch_gmres_solve_small(q, m, jd, H, g, y, s));
-    GC(launch_basis_combine(q, n, jd, Zb, vs, y, u, s));
+    GC(hipMemcpyAsync(hstate.data(), state, 3 * q * sizeof(int), hipMemcpyDeviceToHost, s));
+    GC(hipStreamSynchronize(s));
+    for (int k = 0; k < q; ++k) iters[k] = hstate[2 * q + k];
+    GC(launch_gmres_solve_small(q, m, state + q, H, g, y, s));
+    GC(launch_basis_combine(q, n, state + q, Zb, vs, y, u, s));
     GC(launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, u, b, W, 1, s));
     GT(norms(c, q, n, W, tmp, beta));
   }

@@ -65,6 +65,15 @@ template <typename T> __device__ __forceinline__ typename cvec<T>::type from_c12
 template <> __device__ __forceinline__ double2 from_c128<double>(double2 a) { return a; }
 template <> __device__ __forceinline__ float2 from_c128<float>(double2 a) { return to_c64(a); }
 
+// Work-group barrier that orders LDS accesses only: outstanding global loads
+// (prefetches) stay in flight across it, unlike __syncthreads().  Valid only
+// where threads exchange data through LDS alone.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Box descriptor shared by all batched kernels of one level.  All node ranges
 // are inclusive global node coordinates (p along x, q along y); a box's local
 // vector is p-major: local index (p - p0) * ny + (q - q0).

@@ -4,7 +4,6 @@
 // the restricted prolongation), so C^H t and C y are independent per box and
 // A_c is block-sparse: block (i, j) is non-zero only when the owned box of i
 // meets the owned box of j dilated by the 5-point stencil.
-#include "dense.h"
 #include "kernels.h"
 
 namespace {
@@ -88,91 +87,218 @@ __global__ void __launch_bounds__(TB) k_galerkin_blocks(const BoxDev* __restrict
   }
 }
 
-__global__ void __launch_bounds__(TB) k_gj(const ParentDev* __restrict__ pars, c128* __restrict__ A,
-                                           int* __restrict__ perm_all, int max_nc, int* __restrict__ info) {
+// Gauss-Jordan inversion of every parent's A_c spread over the whole GPU: one
+// launch per pivot selects and interchanges the pivot row, scales it and saves
+// the pivot column; a second launch eliminates the column from all other rows
+// with one thread per matrix entry.
+__global__ void __launch_bounds__(TB) k_gj_pivot(const ParentDev* __restrict__ pars, c128* __restrict__ Aall,
+                                                 int* __restrict__ perm_all, c128* __restrict__ fcol_all, int max_nc,
+                                                 int kk, int* __restrict__ info) {
   const ParentDev P = pars[blockIdx.x];
   const int n = P.n_c;
-  extern __shared__ unsigned char smem_raw[];
-  double2* fcol = reinterpret_cast<double2*>(smem_raw);  // max_nc
-  double* rv = reinterpret_cast<double*>(fcol + max_nc);  // TB
-  int* ri = reinterpret_cast<int*>(rv + TB);               // TB
-  __shared__ double2 s_inv;
-  __shared__ int s_flag;
-  if (threadIdx.x == 0) s_flag = 0;
-  __syncthreads();
-  if (n > 0) gj_inverse_inplace<TB>(A + P.aoff, n, fcol, perm_all + (long long)blockIdx.x * max_nc, rv, ri, &s_inv,
-                                    &s_flag);
-  if (threadIdx.x == 0 && info) info[blockIdx.x] = s_flag;
-}
-
-// cvec[par][b][cidx + k] = C_child[k]^H t[par][b][owned nodes of child]
-__global__ void __launch_bounds__(TB) k_coarse_restrict(const BoxDev* __restrict__ child,
-                                                        const BoxDev* __restrict__ par,
-                                                        const ParentDev* __restrict__ pd, int rmax, int q,
-                                                        const c128* __restrict__ C, const c128* __restrict__ t,
-                                                        c128* __restrict__ cvec) {
-  const int box = blockIdx.x / rmax, k = blockIdx.x % rmax;
-  const int col = blockIdx.y;
-  const BoxDev B = child[box];
-  if (k >= B.r) return;
-  const BoxDev P = par[B.parent];
-  const ParentDev D = pd[B.parent];
-  const c128* c = C + B.coff + (long long)k * B.n_own;
-  const c128* tv = t + P.voff * q + (long long)col * P.n;
-  double2 acc = mk(0.0, 0.0);
-  for (int e = threadIdx.x; e < B.n_own; e += TB) {
-    const int oa = e / B.own_ny, oc = e - oa * B.own_ny;
-    const long long pl = (long long)(B.op0 + oa - P.p0) * P.ny + (B.oq0 + oc - P.q0);
-    acc = cfmac(c[e], tv[pl], acc);
+  if (kk >= n) return;
+  c128* A = Aall + P.aoff;
+  int* perm = perm_all + (long long)blockIdx.x * max_nc;
+  c128* fcol = fcol_all + (long long)blockIdx.x * max_nc;
+  const int tid = threadIdx.x;
+  __shared__ double rv[TB];
+  __shared__ int ri[TB];
+  double best = -1.0;
+  int bi = kk;
+  for (int i = kk + tid; i < n; i += TB) {
+    const double a = cabs2(A[i + (long long)kk * n]);
+    if (a > best) { best = a; bi = i; }
   }
-  __shared__ double sx[TB], sy[TB];
-  sx[threadIdx.x] = acc.x;
-  sy[threadIdx.x] = acc.y;
+  rv[tid] = best;
+  ri[tid] = bi;
   __syncthreads();
   for (int st = TB / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      sx[threadIdx.x] += sx[threadIdx.x + st];
-      sy[threadIdx.x] += sy[threadIdx.x + st];
+    if (tid < st) {
+      const double o = rv[tid + st];
+      const int oi = ri[tid + st];
+      if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) cvec[D.yoff * q + (long long)col * D.n_c + B.cidx + k] = mk(sx[0], sy[0]);
+  const int pr = ri[0];
+  if (tid == 0) {
+    perm[kk] = pr;
+    if (rv[0] <= 0.0 && info[blockIdx.x] == 0) info[blockIdx.x] = kk + 1;
+  }
+  if (pr != kk) {
+    for (int c = tid; c < n; c += TB) {
+      const double2 t = A[kk + (long long)c * n];
+      A[kk + (long long)c * n] = A[pr + (long long)c * n];
+      A[pr + (long long)c * n] = t;
+    }
+  }
+  __syncthreads();
+  const double2 pv = A[kk + (long long)kk * n];
+  const double2 inv = cabs2(pv) > 0.0 ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+  for (int i = tid; i < n; i += TB) fcol[i] = (i == kk) ? mk(0.0, 0.0) : A[i + (long long)kk * n];
+  __syncthreads();
+  for (int c = tid; c < n; c += TB) {
+    const long long e = kk + (long long)c * n;
+    A[e] = (c == kk) ? inv : cmul(A[e], inv);
+  }
 }
 
+__global__ void __launch_bounds__(TB) k_gj_elim(const ParentDev* __restrict__ pars, c128* __restrict__ Aall,
+                                                const c128* __restrict__ fcol_all, int max_nc, int kk) {
+  const ParentDev P = pars[blockIdx.y];
+  const int n = P.n_c;
+  if (kk >= n) return;
+  c128* A = Aall + P.aoff;
+  const c128* fcol = fcol_all + (long long)blockIdx.y * max_nc;
+  const long long nn = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)TB + threadIdx.x; e < nn; e += (long long)gridDim.x * TB) {
+    const int i = (int)(e % n), c = (int)(e / n);
+    if (i == kk) continue;
+    const double2 base = (c == kk) ? mk(0.0, 0.0) : A[e];
+    A[e] = csub(base, cmul(fcol[i], A[kk + (long long)c * n]));
+  }
+}
+
+// undo the row interchanges as column interchanges (last first), one row per thread
+__global__ void __launch_bounds__(TB) k_gj_unperm(const ParentDev* __restrict__ pars, c128* __restrict__ Aall,
+                                                  const int* __restrict__ perm_all, int max_nc) {
+  const ParentDev P = pars[blockIdx.y];
+  const int n = P.n_c;
+  c128* A = Aall + P.aoff;
+  const int* perm = perm_all + (long long)blockIdx.y * max_nc;
+  const int i = blockIdx.x * TB + threadIdx.x;
+  if (i >= n) return;
+  for (int kk = n - 1; kk >= 0; --kk) {
+    const int pk = perm[kk];
+    if (pk != kk) {
+      const double2 t = A[i + (long long)kk * n];
+      A[i + (long long)kk * n] = A[i + (long long)pk * n];
+      A[i + (long long)pk * n] = t;
+    }
+  }
+}
+
+// cvec[par][b][cidx + k] = C_child[k]^H t[par][b][owned nodes of child];
+// block (child, group of KC columns, chunk of QC right-hand sides), so C is
+// read q/QC times and t r/KC times.
+constexpr int KC = 4, QC = 8;
+
+__global__ void __launch_bounds__(TB) k_coarse_restrict(const BoxDev* __restrict__ child,
+                                                        const BoxDev* __restrict__ par,
+                                                        const ParentDev* __restrict__ pd, int kgroups, int q,
+                                                        const c128* __restrict__ C, const c128* __restrict__ t,
+                                                        c128* __restrict__ cvec) {
+  const int box = blockIdx.x / kgroups, k0 = (blockIdx.x % kgroups) * KC;
+  const int b0 = blockIdx.y * QC;
+  const BoxDev B = child[box];
+  if (k0 >= B.r) return;
+  const BoxDev P = par[B.parent];
+  const ParentDev D = pd[B.parent];
+  double2 acc[KC][QC];
+#pragma unroll
+  for (int a = 0; a < KC; ++a)
+#pragma unroll
+    for (int c = 0; c < QC; ++c) acc[a][c] = mk(0.0, 0.0);
+  for (int e = threadIdx.x; e < B.n_own; e += TB) {
+    const int oa = e / B.own_ny, oc = e - oa * B.own_ny;
+    const long long pl = (long long)(B.op0 + oa - P.p0) * P.ny + (B.oq0 + oc - P.q0);
+    double2 cv[KC];
+#pragma unroll
+    for (int a = 0; a < KC; ++a)
+      cv[a] = k0 + a < B.r ? C[B.coff + (long long)(k0 + a) * B.n_own + e] : mk(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < QC; ++c) {
+      if (b0 + c < q) {
+        const double2 tv = t[P.voff * q + (long long)(b0 + c) * P.n + pl];
+#pragma unroll
+        for (int a = 0; a < KC; ++a) acc[a][c] = cfmac(cv[a], tv, acc[a][c]);
+      }
+    }
+  }
+  __shared__ double sx[TB], sy[TB];
+#pragma unroll
+  for (int a = 0; a < KC; ++a)
+#pragma unroll
+    for (int c = 0; c < QC; ++c) {
+      sx[threadIdx.x] = acc[a][c].x;
+      sy[threadIdx.x] = acc[a][c].y;
+      __syncthreads();
+      for (int st = TB / 2; st > 0; st >>= 1) {
+        if (threadIdx.x < st) {
+          sx[threadIdx.x] += sx[threadIdx.x + st];
+          sy[threadIdx.x] += sy[threadIdx.x + st];
+        }
+        __syncthreads();
+      }
+      if (threadIdx.x == 0 && k0 + a < B.r && b0 + c < q)
+        cvec[D.yoff * q + (long long)(b0 + c) * D.n_c + B.cidx + k0 + a] = mk(sx[0], sy[0]);
+      __syncthreads();
+    }
+}
+
+// y[par][b] = A_c^{-1} cvec[par][b]: block (64 rows, parent, rhs), four column
+// slices per row reduced in LDS.
 __global__ void __launch_bounds__(TB) k_coarse_gemv(const ParentDev* __restrict__ pd, int q,
                                                     const c128* __restrict__ Ainv, const c128* __restrict__ cvec,
                                                     c128* __restrict__ y) {
   const int pb = blockIdx.y / q, col = blockIdx.y % q;
   const ParentDev D = pd[pb];
   const int n = D.n_c;
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= n) return;
   const c128* cv = cvec + D.yoff * q + (long long)col * n;
-  c128* yv = y + D.yoff * q + (long long)col * n;
   const c128* A = Ainv + D.aoff;
-  for (int r = blockIdx.x * TB + threadIdx.x; r < n; r += gridDim.x * TB) {
-    double2 acc = mk(0.0, 0.0);
-    for (int c = 0; c < n; ++c) acc = cfma(A[r + (long long)c * n], cv[c], acc);
-    yv[r] = acc;
+  const int rr = threadIdx.x & 63, sl = threadIdx.x >> 6;
+  const int r = r0 + rr;
+  double2 acc = mk(0.0, 0.0);
+  if (r < n)
+    for (int c = sl; c < n; c += 4) acc = cfma(A[r + (long long)c * n], cv[c], acc);
+  __shared__ double2 red[4][64];
+  red[sl][rr] = acc;
+  __syncthreads();
+  if (sl == 0 && r < n) {
+    const double2 s = cadd(cadd(red[0][rr], red[1][rr]), cadd(red[2][rr], red[3][rr]));
+    y[D.yoff * q + (long long)col * n + r] = s;
   }
 }
 
+// u[par][b][owned nodes of child] += C_child y: one thread per owned node, QC
+// right-hand sides per thread so C is read q/QC times.
 __global__ void __launch_bounds__(TB) k_coarse_prolong(const BoxDev* __restrict__ child,
                                                        const BoxDev* __restrict__ par,
                                                        const ParentDev* __restrict__ pd, int q,
                                                        const c128* __restrict__ C, const c128* __restrict__ y,
                                                        c128* __restrict__ u) {
-  const int box = blockIdx.y / q, col = blockIdx.y % q;
+  const int box = blockIdx.y;
+  const int b0 = blockIdx.z * QC;
   const BoxDev B = child[box];
   if (B.r == 0) return;
   const BoxDev P = par[B.parent];
   const ParentDev D = pd[B.parent];
-  const c128* yv = y + D.yoff * q + (long long)col * D.n_c + B.cidx;
-  c128* uv = u + P.voff * q + (long long)col * P.n;
+  __shared__ double2 ys[QC][128];
+  for (int e = threadIdx.x; e < QC * B.r; e += TB) {
+    const int c = e / B.r, k = e % B.r;
+    ys[c][k] = b0 + c < q ? y[D.yoff * q + (long long)(b0 + c) * D.n_c + B.cidx + k] : mk(0.0, 0.0);
+  }
+  __syncthreads();
   for (int e = blockIdx.x * TB + threadIdx.x; e < B.n_own; e += gridDim.x * TB) {
-    double2 acc = mk(0.0, 0.0);
-    for (int k = 0; k < B.r; ++k) acc = cfma(C[B.coff + (long long)k * B.n_own + e], yv[k], acc);
+    double2 acc[QC];
+#pragma unroll
+    for (int c = 0; c < QC; ++c) acc[c] = mk(0.0, 0.0);
+    for (int k = 0; k < B.r; ++k) {
+      const double2 cv = C[B.coff + (long long)k * B.n_own + e];
+#pragma unroll
+      for (int c = 0; c < QC; ++c) acc[c] = cfma(cv, ys[c][k], acc[c]);
+    }
     const int oa = e / B.own_ny, oc = e - oa * B.own_ny;
     const long long pl = (long long)(B.op0 + oa - P.p0) * P.ny + (B.oq0 + oc - P.q0);
-    uv[pl] = cadd(uv[pl], acc);
+#pragma unroll
+    for (int c = 0; c < QC; ++c) {
+      if (b0 + c < q) {
+        c128* uv = u + P.voff * q + (long long)(b0 + c) * P.n;
+        uv[pl] = cadd(uv[pl], acc[c]);
+      }
+    }
   }
 }
 
@@ -200,26 +326,34 @@ hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, co
   return hipGetLastError();
 }
 
-hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, int* info,
+hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, c128* fcol, int* info,
                              hipStream_t s) {
   if (npar <= 0 || max_nc <= 0) return hipSuccess;
-  const size_t shm = sizeof(double2) * max_nc + (sizeof(double) + sizeof(int)) * TB;
-  hipLaunchKernelGGL(k_gj, dim3(npar), dim3(TB), shm, s, pars, A, piv, max_nc, info);
+  hipError_t e = launch_fill_zero(info, (long long)sizeof(int) * npar, s);
+  if (e != hipSuccess) return e;
+  const long long nn = (long long)max_nc * max_nc;
+  const int gxe = gx(nn, 1024);
+  for (int kk = 0; kk < max_nc; ++kk) {
+    hipLaunchKernelGGL(k_gj_pivot, dim3(npar), dim3(TB), 0, s, pars, A, piv, fcol, max_nc, kk, info);
+    hipLaunchKernelGGL(k_gj_elim, dim3(gxe, npar), dim3(TB), 0, s, pars, A, fcol, max_nc, kk);
+  }
+  hipLaunchKernelGGL(k_gj_unperm, dim3((max_nc + TB - 1) / TB, npar), dim3(TB), 0, s, pars, A, piv, max_nc);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const BoxDev* par, const ParentDev* pd,
                                   int rmax, int q, const c128* C, const c128* t, c128* cvec, hipStream_t s) {
   if (nchild <= 0 || rmax <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_restrict, dim3(nchild * rmax, q), dim3(TB), 0, s, child, par, pd, rmax, q, C, t,
-                     cvec);
+  const int kgroups = (rmax + KC - 1) / KC;
+  hipLaunchKernelGGL(k_coarse_restrict, dim3(nchild * kgroups, (q + QC - 1) / QC), dim3(TB), 0, s, child, par, pd,
+                     kgroups, q, C, t, cvec);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, const c128* Ainv,
                               const c128* cvec, c128* y, hipStream_t s) {
   if (npar <= 0 || max_nc <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_gemv, dim3(gx(max_nc, 64), npar * q), dim3(TB), 0, s, pd, q, Ainv, cvec, y);
+  hipLaunchKernelGGL(k_coarse_gemv, dim3((max_nc + 63) / 64, npar * q), dim3(TB), 0, s, pd, q, Ainv, cvec, y);
   return hipGetLastError();
 }
 
@@ -227,7 +361,7 @@ hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, c
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
                                  hipStream_t s) {
   if (nchild <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_prolong, dim3(gx(max_own, 256), nchild * q), dim3(TB), 0, s, child, par, pd, q, C, y,
-                     u);
+  hipLaunchKernelGGL(k_coarse_prolong, dim3(gx(max_own, 256), nchild, (q + QC - 1) / QC), dim3(TB), 0, s, child,
+                     par, pd, q, C, y, u);
   return hipGetLastError();
 }

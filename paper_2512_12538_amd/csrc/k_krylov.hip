@@ -2,14 +2,17 @@
 // reduction tree (the split into blocks depends on the vector length only, so
 // a right-hand side gets bit-identical results alone and inside any batch),
 // the Gram-Schmidt updates, and the per-right-hand-side GMRES bookkeeping
-// (Givens rotations of the Hessenberg column, the small triangular solve).
+// (Givens rotations of the Hessenberg column, the convergence test, the small
+// triangular solve).  The convergence decision is taken on the device so the
+// host can poll it without draining the stream.
 #include "kernels.h"
 
 namespace {
 
 constexpr int TB = 256;
-constexpr int CHUNK = 4096;  // nodes per partial sum
+constexpr int CHUNK = 1024;  // nodes per partial sum
 constexpr int MAXNB = 512;
+constexpr int KG = 8;        // inner products per block
 
 inline int nblocks(long long n) {
   long long nb = (n + CHUNK - 1) / CHUNK;
@@ -18,20 +21,9 @@ inline int nblocks(long long n) {
   return (int)nb;
 }
 
-// partial[(k*q + b)*NB + blk] = sum over the block's chunk of conj(V_k[b]) W[b]
-__global__ void __launch_bounds__(TB) k_dot_partial(int q, long long n, int NB, const c128* __restrict__ V,
-                                                    long long vstride, const c128* __restrict__ W,
-                                                    c128* __restrict__ partial) {
-  const int blk = blockIdx.x, k = blockIdx.y, b = blockIdx.z;
-  const long long per = (n + NB - 1) / NB;
-  const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
-  const c128* v = V + k * vstride + (long long)b * n;
-  const c128* w = W + (long long)b * n;
-  double2 acc = mk(0.0, 0.0);
-  for (long long i = lo + threadIdx.x; i < hi; i += TB) acc = cfmac(v[i], w[i], acc);
-  __shared__ double sx[TB], sy[TB];
-  sx[threadIdx.x] = acc.x;
-  sy[threadIdx.x] = acc.y;
+__device__ __forceinline__ double2 block_sum(double2 v, double* sx, double* sy) {
+  sx[threadIdx.x] = v.x;
+  sy[threadIdx.x] = v.y;
   __syncthreads();
   for (int st = TB / 2; st > 0; st >>= 1) {
     if (threadIdx.x < st) {
@@ -40,7 +32,35 @@ __global__ void __launch_bounds__(TB) k_dot_partial(int q, long long n, int NB, 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) partial[((long long)k * q + b) * NB + blk] = mk(sx[0], sy[0]);
+  const double2 r = mk(sx[0], sy[0]);
+  __syncthreads();
+  return r;
+}
+
+// partial[((k*q + b)*NB + blk] = sum over the block's chunk of conj(V_k[b]) W[b],
+// KG consecutive k per block so that W is read once per KG products.
+__global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, int NB, const c128* __restrict__ V,
+                                                    long long vstride, const c128* __restrict__ W,
+                                                    c128* __restrict__ partial) {
+  const int blk = blockIdx.x, k0 = blockIdx.y * KG, b = blockIdx.z;
+  const long long per = (n + NB - 1) / NB;
+  const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
+  const c128* w = W + (long long)b * n;
+  double2 acc[KG];
+#pragma unroll
+  for (int t = 0; t < KG; ++t) acc[t] = mk(0.0, 0.0);
+  for (long long i = lo + threadIdx.x; i < hi; i += TB) {
+    const double2 wv = w[i];
+#pragma unroll
+    for (int t = 0; t < KG; ++t)
+      if (k0 + t < nk) acc[t] = cfmac(V[(k0 + t) * vstride + (long long)b * n + i], wv, acc[t]);
+  }
+  __shared__ double sx[TB], sy[TB];
+#pragma unroll
+  for (int t = 0; t < KG; ++t) {
+    const double2 r = block_sum(acc[t], sx, sy);
+    if (threadIdx.x == 0 && k0 + t < nk) partial[((long long)(k0 + t) * q + b) * NB + blk] = r;
+  }
 }
 
 __global__ void k_dot_final(int nkq, int NB, const c128* __restrict__ partial, c128* __restrict__ out) {
@@ -51,14 +71,39 @@ __global__ void k_dot_final(int nkq, int NB, const c128* __restrict__ partial, c
   out[t] = acc;
 }
 
-__global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n, const c128* __restrict__ V,
+// W[b] -= sum_k V_k[b] h[k*q + b]; optionally the block partial sums of |W[b]|^2
+// after the update (same chunking as the inner products).  Coefficients sit in
+// LDS; the k loop is unrolled by four so four basis loads are in flight.
+__global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n, int NB, const c128* __restrict__ V,
                                                      long long vstride, const c128* __restrict__ h,
-                                                     c128* __restrict__ W) {
-  const int b = blockIdx.y;
-  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
+                                                     c128* __restrict__ W, c128* __restrict__ npart) {
+  const int blk = blockIdx.x, b = blockIdx.y;
+  __shared__ double2 hs[128];
+  for (int k = threadIdx.x; k < nk; k += TB) hs[k] = h[k * q + b];
+  __syncthreads();
+  const long long per = (n + NB - 1) / NB;
+  const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
+  const c128* vb = V + (long long)b * n;
+  double nrm = 0.0;
+  for (long long i = lo + threadIdx.x; i < hi; i += TB) {
     double2 w = W[(long long)b * n + i];
-    for (int k = 0; k < nk; ++k) w = csub(w, cmul(V[k * vstride + (long long)b * n + i], h[k * q + b]));
+    int k = 0;
+    for (; k + 4 <= nk; k += 4) {
+      const double2 v0 = vb[(k + 0) * vstride + i], v1 = vb[(k + 1) * vstride + i];
+      const double2 v2 = vb[(k + 2) * vstride + i], v3 = vb[(k + 3) * vstride + i];
+      w = csub(w, cmul(v0, hs[k + 0]));
+      w = csub(w, cmul(v1, hs[k + 1]));
+      w = csub(w, cmul(v2, hs[k + 2]));
+      w = csub(w, cmul(v3, hs[k + 3]));
+    }
+    for (; k < nk; ++k) w = csub(w, cmul(vb[k * vstride + i], hs[k]));
     W[(long long)b * n + i] = w;
+    nrm += cabs2(w);
+  }
+  if (npart) {
+    __shared__ double sx[TB], sy[TB];
+    const double2 r = block_sum(mk(nrm, 0.0), sx, sy);
+    if (threadIdx.x == 0) npart[(long long)b * NB + blk] = r;
   }
 }
 
@@ -74,15 +119,20 @@ __global__ void __launch_bounds__(TB) k_normalize(int q, long long n, const c128
 }
 
 // One Arnoldi column per right-hand side: H[:, j] = h1 + h2, H[j+1, j] = ||w||,
-// previous rotations, a new rotation zeroing H[j+1, j], and the update of g.
+// previous rotations, a new rotation zeroing H[j+1, j], the update of g, and
+// the stopping test |g_{j+1}| < thr[b] or iters[b] >= maxit.
 // Layout per rhs b: H[b][(m+1)*col + row], cs/sn[b][m], g[b][m+1].
 __global__ void k_gmres_step(int q, int j, int m, c128* __restrict__ H, const c128* __restrict__ h1,
                              const c128* __restrict__ h2, const double* __restrict__ hnext,
                              c128* __restrict__ cs, c128* __restrict__ sn, c128* __restrict__ g,
-                             double* __restrict__ est, const int* __restrict__ active) {
+                             double* __restrict__ est, int* __restrict__ st, const double* __restrict__ thr,
+                             int maxit) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= q) return;
-  if (active && !active[b]) return;
+  int* active = st;
+  int* jdone = st + q;
+  int* iters = st + 2 * q;
+  if (!active[b]) return;
   c128* Hb = H + (long long)b * (m + 1) * m;
   c128* cb = cs + (long long)b * m;
   c128* sb = sn + (long long)b * m;
@@ -112,7 +162,22 @@ __global__ void k_gmres_step(int q, int j, int m, c128* __restrict__ H, const c1
   const double2 gj = gb[j];
   gb[j + 1] = mk(-(s.x * gj.x - s.y * gj.y), -(s.x * gj.y + s.y * gj.x));
   gb[j] = cmulc(c, gj);
-  est[b] = sqrt(cabs2(gb[j + 1]));
+  const double e = sqrt(cabs2(gb[j + 1]));
+  est[b] = e;
+  jdone[b] = j + 1;
+  iters[b] += 1;
+  if (e < thr[b] || iters[b] >= maxit) active[b] = 0;
+}
+
+// any[0] = number of active right-hand sides
+__global__ void k_count_active(int q, const int* __restrict__ st, int* __restrict__ any) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int b = threadIdx.x; b < q; b += blockDim.x)
+    if (st[b]) atomicAdd(&cnt, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) any[0] = cnt;
 }
 
 // y[k*q + b] for k < jdone[b]: back substitution with the rotated (upper
@@ -159,16 +224,20 @@ hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long 
                            c128* partial, c128* out, hipStream_t s) {
   if (nk <= 0 || q <= 0) return hipSuccess;
   const int NB = nblocks(n);
-  hipLaunchKernelGGL(k_dot_partial, dim3(NB, nk, q), dim3(TB), 0, s, q, n, NB, V, vstride, W, partial);
+  hipLaunchKernelGGL(k_dot_partial, dim3(NB, (nk + KG - 1) / KG, q), dim3(TB), 0, s, nk, q, n, NB, V, vstride, W,
+                     partial);
   const int nkq = nk * q;
   hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, NB, partial, out);
   return hipGetLastError();
 }
 
-hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h,
-                               c128* W, hipStream_t s) {
+hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h, c128* W,
+                               c128* partial, c128* nrm2, hipStream_t s) {
   if (nk <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_basis_update, dim3(gx(n, 1024), q), dim3(TB), 0, s, nk, q, n, V, vstride, h, W);
+  const int NB = nblocks(n);
+  hipLaunchKernelGGL(k_basis_update, dim3(NB, q), dim3(TB), 0, s, nk, q, n, NB, V, vstride, h, W,
+                     nrm2 ? partial : nullptr);
+  if (nrm2) hipLaunchKernelGGL(k_dot_final, dim3((q + 127) / 128), dim3(128), 0, s, q, NB, partial, nrm2);
   return hipGetLastError();
 }
 
@@ -180,10 +249,12 @@ hipError_t launch_normalize(int q, long long n, const c128* nrm2, const c128* x,
 }
 
 hipError_t launch_gmres_step(int q, int j, int m, c128* H, const c128* h1, const c128* h2, const double* hnext,
-                             c128* cs, c128* sn, c128* g, double* est, const int* active, hipStream_t s) {
+                             c128* cs, c128* sn, c128* g, double* est, int* state, const double* thr, int maxit,
+                             int* any, hipStream_t s) {
   if (q <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_gmres_step, dim3((q + 63) / 64), dim3(64), 0, s, q, j, m, H, h1, h2, hnext, cs, sn, g, est,
-                     active);
+                     state, thr, maxit);
+  hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, q, state, any);
   return hipGetLastError();
 }
 

@@ -69,7 +69,9 @@ hipError_t launch_galerkin_ac(const OpDev& op, const BoxDev* boxes, int nbox, co
 hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, const int4* pairs, int npairs,
                                   int rmax, const int4* dil, const c128* C, const c128* AC, c128* Ac,
                                   hipStream_t s);
-hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, int* info,
+// In-place inverse of every parent's A_c (Gauss-Jordan, partial pivoting); piv and fcol hold
+// npar*max_nc entries; info[p] = first zero pivot + 1 (0 if none)
+hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, c128* fcol, int* info,
                              hipStream_t s);
 hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const BoxDev* par, const ParentDev* pd,
                                   int rmax, int q, const c128* C, const c128* t, c128* cvec, hipStream_t s);
@@ -84,14 +86,18 @@ int multidot_nblocks(long long n);
 // out[k*q + b] = sum_x conj(V_k[b][x]) W[b][x], k < nk (V_k at V + k*vstride); partial: nk*q*NB entries
 hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long vstride, const c128* W,
                            c128* partial, c128* out, hipStream_t s);
-// W[b] -= sum_k V_k[b] h[k*q + b]
-hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h,
-                               c128* W, hipStream_t s);
+// W[b] -= sum_k V_k[b] h[k*q + b]; if nrm2 is non-null also nrm2[b] = ||W[b]||^2 after the update
+// (partial: q*NB scratch entries)
+hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h, c128* W,
+                               c128* partial, c128* nrm2, hipStream_t s);
 // y[b] = x[b] / sqrt(re nrm2[b]) (zero if the norm is zero); nrm[b] = the norm
 hipError_t launch_normalize(int q, long long n, const c128* nrm2, const c128* x, c128* y, double* nrm,
                             hipStream_t s);
+// GMRES column j for every active rhs; state = [active[q], jdone[q], iters[q]]; a rhs turns
+// inactive when |g_{j+1}| < thr[b] or iters >= maxit; any[0] = number still active
 hipError_t launch_gmres_step(int q, int j, int m, c128* H, const c128* h1, const c128* h2, const double* hnext,
-                             c128* cs, c128* sn, c128* g, double* est, const int* active, hipStream_t s);
+                             c128* cs, c128* sn, c128* g, double* est, int* state, const double* thr, int maxit,
+                             int* any, hipStream_t s);
 hipError_t launch_gmres_solve_small(int q, int m, const int* jdone, const c128* H, const c128* g, c128* y,
                                     hipStream_t s);
 hipError_t launch_basis_combine(int q, long long n, const int* jdone, const c128* Z, long long zstride,
