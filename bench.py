@@ -8,8 +8,8 @@ seeded smoothed complex Gaussian right-hand sides.  A step runs the whole
 path: hh_setup (leaf factorisations), hh_build_coarse (sketch, QR, adjoint,
 small SVD, extension, Galerkin A_c and its inverse) and hh_solve (GMRES(50)
 around the ORAS + coarse preconditioner) to a relative residual of 1e-8 for
-every right-hand side.  Inputs (RHS batch, Gaussian blocks) are resident in
-HBM before the timed region.
+every right-hand side.  Inputs (the RHS batch, the Gaussian blocks) are
+resident in HBM before the timed region.
 
 Prints one JSON line.  `--gpus N` with N > 1 exits: this path runs on one GPU.
 """
@@ -30,6 +30,12 @@ if ROOT not in sys.path:
 
 METRIC = "Helmholtz solves/s at 1e-8 rel. residual, mixed vs FP64 plain; p99 latency"
 HBM_PEAK_GBS = 8000.0
+# vector FP64 FMA rate, and FP32 without packed instructions (the build disables them):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
+VALU_PEAK_TFS = 78.6
+CFG = dict(N=256, k=40.0, m=[(4, 4)], overlap=[4], rank=8, oversample=10, rtol=1e-8, maxit=500, restart=50)
+FAMILY = {0: "k_leaf_solve (block-tridiagonal sweeps)", 1: "k_basis_update (Gram-Schmidt)",
+          2: "k_dot_partial (Gram-Schmidt inner products)"}
 
 
 def parse():
@@ -37,35 +43,47 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--nrhs", type=int, default=16)
+    ap.add_argument("--nrhs", type=int, default=64)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the secondary mixed-precision measurement")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-profile", action="store_true", help="no live kernel events in the timed region")
     ap.add_argument("--cpu-rhs", type=int, default=2, help="right-hand sides in the CPU oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     return ap.parse_args()
 
 
-CFG = dict(N=256, k=40.0, m=[(4, 4)], overlap=[4], rank=8, oversample=10, rtol=1e-8, maxit=500, restart=50)
-
-
-def make_inputs(hh, torch, ctx_probe, nrhs, seed=1):
+def make_inputs(hh, torch, nrhs, seed=1):
     import workloads as W
 
+    probe = hh.hh_setup(2, CFG["N"], CFG["k"], hh.decomposition(CFG["m"], CFG["overlap"]))
+    m_in, _, s = hh.hh_level_info(probe, 1, CFG["rank"], CFG["oversample"])
+    hh.hh_destroy(probe)
     f = W.smoothed_gaussian_rhs(CFG["N"], seed, nrhs)
-    m_in, _, s = hh.hh_level_info(ctx_probe, 1, CFG["rank"], CFG["oversample"])
     om = np.concatenate([W.omega_block(0, 1, i, int(m_in[i]), int(s[i])).reshape(-1) for i in range(len(m_in))])
     return torch.from_numpy(f).to("cuda"), torch.from_numpy(om).to("cuda"), f
 
 
-def one_step(hh, torch, fd, om, u, precision, phases=None):
+def one_step(hh, fd, om, u, precision, phases=None, prof=None):
     t0 = time.perf_counter()
     ctx = hh.hh_setup(2, CFG["N"], CFG["k"], hh.decomposition(CFG["m"], CFG["overlap"]), precision=precision,
                       outer=hh.HH_GMRES, gmres_restart=CFG["restart"])
     t1 = time.perf_counter()
     hh.hh_build_coarse(ctx, 1, CFG["rank"], CFG["oversample"], om)
     t2 = time.perf_counter()
+    if prof is not None:
+        hh.hh_profile(ctx, True)
     info = hh.hh_solve(ctx, fd, u, CFG["rtol"], CFG["maxit"], raise_on_notconv=True)
     t3 = time.perf_counter()
+    if prof is not None:
+        for fam in FAMILY:
+            n, ms, by, fl = hh.hh_profile_read(ctx, fam)
+            acc = prof.setdefault(fam, [0, 0.0, 0.0, 0.0])
+            acc[0] += n
+            acc[1] += ms
+            acc[2] += by
+            acc[3] += fl
     hh.hh_destroy(ctx)
     if phases is not None:
         phases["setup"].append(t1 - t0)
@@ -74,35 +92,57 @@ def one_step(hh, torch, fd, om, u, precision, phases=None):
     return info
 
 
-def run_gpu(hh, torch, args, precision, steps, warmup):
-    probe = hh.hh_setup(2, CFG["N"], CFG["k"], hh.decomposition(CFG["m"], CFG["overlap"]))
-    fd, om, f = make_inputs(hh, torch, probe, args.nrhs)
-    hh.hh_destroy(probe)
+def run_gpu(hh, torch, nrhs, precision, steps, warmup, profile):
+    fd, om, f = make_inputs(hh, torch, nrhs)
     u = torch.zeros_like(fd)
     for _ in range(warmup):
-        one_step(hh, torch, fd, om, u, precision)
+        one_step(hh, fd, om, u, precision)
     torch.cuda.synchronize()
     phases = {"setup": [], "build_coarse": [], "solve": []}
+    prof = {} if profile else None
     lat = []
     iters = None
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    t_wall0 = time.perf_counter()
-    start.record()
+    t0 = time.perf_counter()
     for _ in range(steps):
         ts = time.perf_counter()
-        info = one_step(hh, torch, fd, om, u, precision, phases)
+        info = one_step(hh, fd, om, u, precision, phases, prof)
         lat.append(time.perf_counter() - ts)
         iters = [i[0] for i in info]
         assert all(i[1] for i in info)
-    stop.record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t_wall0
-    return dict(wall=wall, event_ms=start.elapsed_time(stop), phases=phases, lat=lat, iters=iters, u=u, f=f)
+    wall = time.perf_counter() - t0
+    return dict(wall=wall, phases=phases, lat=lat, iters=iters, u=u, f=f, prof=prof)
+
+
+def roofline(prof, precision):
+    if not prof:
+        return None
+    fam = max(prof, key=lambda k: prof[k][1])
+    n, ms, by, fl = prof[fam]
+    if n == 0:
+        return None
+    avg_s = ms / n / 1000.0
+    bytes_launch = by / n
+    flops_launch = fl / n
+    intensity = fl / by if by else 0.0
+    ridge = VALU_PEAK_TFS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if fam == 0 and intensity >= ridge:
+        achieved = flops_launch / avg_s / 1e12
+        out = {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TFS, "unit": "TFLOP/s",
+               "frac": round(achieved / VALU_PEAK_TFS, 4)}
+    else:
+        achieved = bytes_launch / avg_s / 1e9
+        out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    out.update({"traffic": None, "kernel": FAMILY[fam], "launches": int(n),
+                "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(bytes_launch),
+                "algorithmic_flops_per_launch": round(flops_launch), "intensity_flop_per_byte": round(intensity, 2),
+                "other_families_ms": {FAMILY[k]: round(v[1], 2) for k, v in prof.items() if k != fam}})
+    return out
 
 
 def cpu_baseline(nrhs):
-    """The FP64 oracle on a bounded sample: setup + coarse build + GMRES for nrhs right-hand sides."""
+    """The FP64 oracle on a bounded sample: one full step (setup, coarse build, GMRES) for nrhs right-hand sides."""
     import workloads as W
     from oracle import krylov
     from oracle.schwarz import HierarchicalORAS
@@ -129,28 +169,43 @@ def cpu_baseline(nrhs):
                                 restart=CFG["restart"])
         its.append(info.iters)
     dt = time.perf_counter() - t0
-    return dict(value=nrhs / dt, unit="solves/s", cores=int(cores), kind="oracle",
-                sample=f"one full step (setup + coarse build + GMRES to 1e-8) for {nrhs} right-hand sides of the "
-                       f"same workload, {dt:.1f} s, iterations {its}")
+    return dict(value=round(nrhs / dt, 4), unit="solves/s", cores=int(cores), kind="oracle",
+                sample=f"one full step (setup + coarse build + GMRES to 1e-8) of the same workload for {nrhs} "
+                       f"right-hand sides, {dt:.1f} s, GMRES iterations {its}; BLAS threads = cores, SuperLU "
+                       f"single-threaded")
+
+
+def copy_calibration(torch):
+    n = 1 << 26  # 1 GiB of complex128
+    x = torch.ones(n, dtype=torch.complex128, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 16, "launches": 3}), flush=True)
 
 
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this path runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design note only)", file=sys.stderr)
+              "(multi-GPU sharding is a design note only)", file=sys.stderr)
         sys.exit(2)
     import torch
-
-    import paper_2512_12538_amd as hh
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
+    import paper_2512_12538_amd as hh
+
     prec = hh.HH_MIXED if args.precision == "mixed" else hh.HH_FP64
-    res = run_gpu(hh, torch, args, prec, args.steps, args.warmup)
-    ms_per_step = res["event_ms"] / args.steps
-    value = args.nrhs * args.steps / (res["event_ms"] / 1000.0)
+    res = run_gpu(hh, torch, args.nrhs, prec, args.steps, args.warmup, not args.no_profile)
+    wall = res["wall"]
+    ms_per_step = 1000.0 * wall / args.steps
+    value = args.nrhs * args.steps / wall
     lat = np.array(res["lat"]) * 1000.0
     out = {
         "metric": METRIC,
@@ -170,22 +225,25 @@ def main():
             "grid_cells": CFG["N"], "k": CFG["k"], "decomposition": "[4x4]", "overlap_cells": 4,
             "rank_per_interface": CFG["rank"], "oversample": CFG["oversample"], "rhs_per_step": args.nrhs,
             "outer": f"gmres({CFG['restart']})", "rtol": CFG["rtol"], "precision": args.precision,
-            "step": "setup + build_coarse + solve of the RHS batch",
+            "step": "hh_setup + hh_build_coarse + hh_solve of the RHS batch",
         },
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
         "phases_ms": {k: round(1000.0 * float(np.mean(v)), 3) for k, v in res["phases"].items()},
-        "gmres_iterations": res["iters"],
+        "gmres_iterations": {"min": int(min(res["iters"])), "max": int(max(res["iters"])),
+                             "mean": round(float(np.mean(res["iters"])), 2)},
+        "solve_only_solves_per_s": round(args.nrhs / float(np.mean(res["phases"]["solve"])), 3),
+        "roofline": roofline(res["prof"], args.precision),
     }
-    out["solve_only_solves_per_s"] = round(args.nrhs / (np.mean(res["phases"]["solve"])), 3)
     if not args.no_mixed and args.precision == "fp64":
-        mres = run_gpu(hh, torch, args, hh.HH_MIXED, max(2, args.steps // 2), 1)
+        mres = run_gpu(hh, torch, args.nrhs, hh.HH_MIXED, max(2, args.steps // 2), 1, False)
         mlat = np.array(mres["lat"]) * 1000.0
         out["mixed"] = {
-            "value": round(args.nrhs * len(mres["lat"]) / (mres["event_ms"] / 1000.0), 3),
+            "value": round(args.nrhs * len(mres["lat"]) / mres["wall"], 3),
             "latency_ms": {"p50": round(float(np.percentile(mlat, 50)), 3),
                            "p99": round(float(np.percentile(mlat, 99)), 3)},
             "phases_ms": {k: round(1000.0 * float(np.mean(v)), 3) for k, v in mres["phases"].items()},
-            "gmres_iterations": mres["iters"],
+            "solve_only_solves_per_s": round(args.nrhs / float(np.mean(mres["phases"]["solve"])), 3),
+            "gmres_iterations_mean": round(float(np.mean(mres["iters"])), 2),
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_rhs)

@@ -82,6 +82,8 @@ typedef struct {
   int32_t precision;     /* hh_precision: HH_MIXED keeps the leaf factors in complex64 */
   int32_t outer;         /* hh_outer used by hh_solve */
   int32_t gmres_restart; /* restart length (default 50 when <= 0, at most 120) */
+  int32_t full_reorth;   /* GMRES Arnoldi: 1 = classical Gram-Schmidt twice at every step;
+                            0 = second pass only where the first cancelled ||w|| by more than 8x */
   void* stream;          /* hipStream_t, or null */
 } hh_options;
 
@@ -145,6 +147,22 @@ hh_status hh_get_coarse(hh_ctx* c, int32_t level, int32_t parent, int32_t* n_c, 
  * parent at level-1) on the box's owned nodes: host c128, r_i columns of
  * n_own entries (owned box p-major).  n_own and r_i returned when non-null. */
 hh_status hh_get_basis(hh_ctx* c, int32_t level, int32_t box, int32_t* n_own, int32_t* r_i, void* C_host);
+
+/* Live kernel timing.  hh_profile(c, 1) clears the counters and brackets every
+ * later launch of the profiled kernel families with HIP events on the
+ * context's stream; hh_profile(c, 0) stops.  hh_profile_read returns, for a
+ * family, the number of launches, their summed event time (ms), and the
+ * summed algorithmic bytes and flops of those launches:
+ *   family 0  leaf block-tridiagonal solve (every G_j streamed once per sweep,
+ *             right-hand side and solution vectors: bytes = sum over leaves of
+ *             (2 nx - 1) b^2 e + 64 q n_i, flops = 8 (2 nx - 1) b^2 q;
+ *             e = 16 bytes for complex128 factors, 8 for complex64)
+ *   family 1  first Gram-Schmidt update W -= V h (bytes 16 n q (j + 3))
+ *   family 2  first Gram-Schmidt inner products V^H W (bytes 16 n q (j + 1 + ceil(j / 8)))
+ * Profiling inserts events between launches; leave it off for timing runs. */
+hh_status hh_profile(hh_ctx* c, int32_t enable);
+hh_status hh_profile_read(hh_ctx* c, int32_t family, int64_t* launches, double* total_ms, double* bytes,
+                          double* flops);
 
 hh_status hh_destroy(hh_ctx* c);
 const char* hh_last_error(const hh_ctx* c);

@@ -3,8 +3,8 @@
 Argument marshalling only: every function forwards to the C ABI of
 ``include/helmdd.h`` with the same name.  Device arrays are torch tensors on
 the GPU (complex128, contiguous); PyTorch provides device memory and the
-stream, nothing else.  Importing this module loads the in-tree
-``libhelmdd.so``; if it has not been built the import fails loudly.
+stream, nothing else.  The in-tree ``libhelmdd.so`` is loaded at the first
+call; if it has not been built that call fails loudly (ImportError).
 """
 
 from __future__ import annotations
@@ -18,7 +18,7 @@ import torch  # load torch's HIP runtime first so the library shares it
 __all__ = [
     "HelmddError", "hh_setup", "hh_level_info", "hh_build_coarse", "hh_solve", "hh_apply_operator",
     "hh_precondition", "hh_get_coarse", "hh_get_basis", "hh_destroy", "decomposition", "library_path",
-    "HH_FP64", "HH_MIXED", "HH_STATIONARY", "HH_GMRES", "Context",
+    "HH_FP64", "HH_MIXED", "HH_STATIONARY", "HH_GMRES", "Context", "hh_profile", "hh_profile_read",
 ]
 
 HH_OK, HH_EINVAL, HH_ENOMEM, HH_EDEVICE, HH_ENOTCONV, HH_ESINGULAR, HH_ESTATE, HH_EUNSUPPORTED = range(8)
@@ -44,7 +44,7 @@ class hh_decomposition(ctypes.Structure):
 
 class hh_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("outer", ctypes.c_int32),
-                ("gmres_restart", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("gmres_restart", ctypes.c_int32), ("full_reorth", ctypes.c_int32), ("stream", ctypes.c_void_p)]
 
 
 class hh_solve_info(ctypes.Structure):
@@ -83,6 +83,8 @@ def _load():
         "hh_get_coarse": [P, i32, i32, P, P, P],
         "hh_get_basis": [P, i32, i32, P, P, P],
         "hh_destroy": [P],
+        "hh_profile": [P, i32],
+        "hh_profile_read": [P, i32, P, P, P, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -93,7 +95,23 @@ def _load():
     return lib
 
 
-_lib = _load()
+class _Lazy:
+    """Loads libhelmdd.so at first use, so that the package imports (and builds) without it."""
+
+    _handle = None
+
+    def __getattr__(self, name):
+        if _Lazy._handle is None:
+            _Lazy._handle = _load()
+        return getattr(_Lazy._handle, name)
+
+
+_lib = _Lazy()
+
+
+def load():
+    """Load the library now (raises ImportError if it has not been built)."""
+    return _lib.hh_setup
 
 
 def _check(status: int, ctx=None) -> None:
@@ -143,7 +161,8 @@ def _vectors(ctx: Context, t: torch.Tensor, name: str) -> int:
 
 
 def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int = HH_FP64,
-             outer: int = HH_GMRES, gmres_restart: int = 50, stream: torch.cuda.Stream | None = None):
+             outer: int = HH_GMRES, gmres_restart: int = 50, stream: torch.cuda.Stream | None = None,
+             full_reorth: bool = False):
     """Returns a Context.  ``k`` is a float or a host array of node wavenumbers."""
     op = hh_operator()
     op.dim = dim
@@ -160,6 +179,7 @@ def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int
     opts.precision = precision
     opts.outer = outer
     opts.gmres_restart = gmres_restart
+    opts.full_reorth = 1 if full_reorth else 0
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = ctypes.c_void_p(st.cuda_stream)
     ctx = ctypes.c_void_p()
@@ -238,6 +258,21 @@ def hh_get_basis(ctx, level: int, box: int) -> np.ndarray:
     if r.value:
         _check(_lib.hh_get_basis(ctx, level, box, None, None, C.ctypes.data_as(ctypes.c_void_p)), ctx)
     return C
+
+
+def hh_profile(ctx, enable: bool) -> None:
+    _check(_lib.hh_profile(ctx, 1 if enable else 0), ctx)
+
+
+def hh_profile_read(ctx, family: int):
+    """(launches, total_ms, algorithmic_bytes, algorithmic_flops) of a kernel family."""
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    by = ctypes.c_double()
+    fl = ctypes.c_double()
+    _check(_lib.hh_profile_read(ctx, family, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)),
+           ctx)
+    return n.value, ms.value, by.value, fl.value
 
 
 def hh_destroy(ctx) -> None:

@@ -75,6 +75,7 @@ struct hh_ctx {
   int precision = HH_FP64;
   int outer = HH_GMRES;
   int restart = 50;
+  double reorth_eta = 0.125;
   Geometry geo;
   OpDev op{};
   double* d_k = nullptr;
@@ -89,6 +90,19 @@ struct hh_ctx {
   std::vector<DevBuf> scratch;
   c128* d_partial = nullptr;
   size_t partial_cap = 0;
+  // live kernel timing (HIP events on the library stream), per kernel family
+  bool prof = false;
+  struct ProfRec {
+    int fam;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<ProfRec> prof_open;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[4] = {0, 0, 0, 0};
+  double prof_bytes[4] = {0, 0, 0, 0};
+  double prof_flops[4] = {0, 0, 0, 0};
+  long long prof_n[4] = {0, 0, 0, 0};
   int* poll = nullptr;          // pinned host words polled by the outer loop
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
   std::vector<void*> allocs;
@@ -208,6 +222,64 @@ hh_status ensure_partial(hh_ctx* c, size_t count) {
   return HH_OK;
 }
 
+// ------------------------------------------------------------------ live kernel timing
+hipEvent_t prof_event(hh_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+struct ProfScope {
+  hh_ctx* c;
+  int fam;
+  double bytes, flops;
+  hipEvent_t a = nullptr;
+  ProfScope(hh_ctx* c_, int fam_, double bytes_, double flops_) : c(c_), fam(fam_), bytes(bytes_), flops(flops_) {
+    if (c->prof && (a = prof_event(c))) (void)hipEventRecord(a, c->stream);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->prof_open.push_back({fam, a, b, bytes, flops});
+  }
+};
+
+// fold finished event pairs into the totals (after a stream synchronisation)
+void prof_collect(hh_ctx* c) {
+  for (auto& r : c->prof_open) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof_ms[r.fam] += ms;
+      c->prof_bytes[r.fam] += r.bytes;
+      c->prof_flops[r.fam] += r.flops;
+      c->prof_n[r.fam] += 1;
+    }
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->prof_open.clear();
+}
+
+// algorithmic traffic and work of one leaf-solve launch over q columns: every
+// G_j streamed once per sweep (2 nx - 1 blocks of b^2), right-hand side read,
+// solution written in the forward sweep, read and written in the backward one
+void leaf_solve_cost(const Level& L, int q, size_t gbytes, double& bytes, double& flops) {
+  bytes = 0.0;
+  flops = 0.0;
+  for (const BoxDev& b : L.hb) {
+    const double bb = (double)b.ny * b.ny;
+    bytes += (2.0 * b.nx - 1.0) * bb * gbytes + 4.0 * q * (double)b.n * 16.0;
+    flops += 8.0 * (2.0 * b.nx - 1.0) * bb * q;
+  }
+}
+
 // ------------------------------------------------------------------ the sweeps
 hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x);
 
@@ -233,6 +305,9 @@ hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
 hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x) {
   Level& Lv = c->lv[l];
   if (l == c->L) {
+    double bytes = 0.0, flops = 0.0;
+    if (c->prof) leaf_solve_cost(Lv, q, c->precision == HH_MIXED ? 8 : 16, bytes, flops);
+    ProfScope ps(c, 0, bytes, flops);
     if (c->precision == HH_MIXED) {
       HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, c->stream));
     } else {
@@ -299,6 +374,11 @@ hh_status hh_destroy(hh_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (int i = 0; i < 2; ++i)
     if (c->poll_ev[i]) (void)hipEventDestroy(c->poll_ev[i]);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (auto& r : c->prof_open) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
   if (c->poll) (void)hipHostFree(c->poll);
   for (void* p : c->allocs) (void)hipFree(p);
   c->allocs.clear();
@@ -326,6 +406,7 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
     c->precision = o->precision == HH_MIXED ? HH_MIXED : HH_FP64;
     c->outer = o->outer == HH_STATIONARY ? HH_STATIONARY : HH_GMRES;
     c->restart = o->gmres_restart > 0 ? std::min(o->gmres_restart, 120) : 50;
+    c->reorth_eta = o->full_reorth ? 2.0 : 0.125;
   }
   std::string msg = build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, c->geo);
   if (!msg.empty()) {
@@ -748,9 +829,10 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
   c128 *Vb = nullptr, *Zb = nullptr, *W = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
   c128 *h1 = nullptr, *h2 = nullptr, *tmp = nullptr, *y = nullptr;
   double *hn = nullptr, *est = nullptr, *thr = nullptr;
-  int *state = nullptr, *any = nullptr;
+  int *state = nullptr, *any = nullptr, *need = nullptr;
   auto cleanup = [&]() {
-    for (void* p : std::initializer_list<void*>{Vb, Zb, W, H, cs, sn, g, h1, h2, tmp, y, hn, est, thr, state, any})
+    for (void* p :
+         std::initializer_list<void*>{Vb, Zb, W, H, cs, sn, g, h1, h2, tmp, y, hn, est, thr, state, any, need})
       dfree(c, p);
   };
   hh_status st = HH_OK;
@@ -762,7 +844,8 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     if ((st = dalloc(c, &cs, (size_t)q * m)) != HH_OK) break;
     if ((st = dalloc(c, &sn, (size_t)q * m)) != HH_OK) break;
     if ((st = dalloc(c, &g, (size_t)q * (m + 1))) != HH_OK) break;
-    if ((st = dalloc(c, &h1, (size_t)q * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &h1, (size_t)q * (m + 2))) != HH_OK) break;
+    if ((st = dalloc(c, &need, (size_t)q)) != HH_OK) break;
     if ((st = dalloc(c, &h2, (size_t)q * (m + 1))) != HH_OK) break;
     if ((st = dalloc(c, &tmp, (size_t)q * (m + 1))) != HH_OK) break;
     if ((st = dalloc(c, &y, (size_t)q * m)) != HH_OK) break;
@@ -771,7 +854,7 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     if ((st = dalloc(c, &thr, (size_t)q)) != HH_OK) break;
     if ((st = dalloc(c, &state, (size_t)3 * q)) != HH_OK) break;
     if ((st = dalloc(c, &any, (size_t)2)) != HH_OK) break;
-    if ((st = ensure_partial(c, (size_t)(m + 1) * q * multidot_nblocks(n))) != HH_OK) break;
+    if ((st = ensure_partial(c, (size_t)(m + 2) * q * multidot_nblocks(n))) != HH_OK) break;
     if ((st = ensure_poll(c)) != HH_OK) break;
   } while (false);
   if (st != HH_OK) {
@@ -827,10 +910,20 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
       GT(two_level(c, 0, q, vj, zj));
       GC(launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, zj, nullptr, W, 0, s));
       // classical Gram-Schmidt twice; the second update also gives ||w||^2
-      GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h1, s));
-      GC(launch_basis_update(j + 1, q, n, Vb, vs, h1, W, nullptr, nullptr, s));
-      GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h2, s));
-      GC(launch_basis_update(j + 1, q, n, Vb, vs, h2, W, c->d_partial, tmp, s));
+      // classical Gram-Schmidt; the second pass runs for the columns whose first
+      // pass cancelled by more than the factor reorth_eta (all columns when >= 1)
+      const double vbytes = 16.0 * (double)n * q;
+      {
+        ProfScope ps(c, 2, vbytes * (j + 1 + (j + 8) / 8), 8.0 * n * q * (j + 1));
+        GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h1, s, 1));
+      }
+      {
+        ProfScope ps(c, 1, vbytes * (j + 3), 8.0 * n * q * (j + 1));
+        GC(launch_basis_update(j + 1, q, n, Vb, vs, h1, W, c->d_partial, tmp, s));
+      }
+      GC(launch_reorth_flag(q, j + 1, h1 + (size_t)(j + 1) * q, tmp, c->reorth_eta, need, h2, s));
+      GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h2, s, 0, need));
+      GC(launch_basis_update(j + 1, q, n, Vb, vs, h2, W, c->d_partial, tmp, s, need));
       GC(launch_normalize(q, n, tmp, W, Vb + (j + 1) * vs, hn, s));
       GC(launch_gmres_step(q, j, m, H, h1, h2, hn, cs, sn, g, est, state, thr, maxit, any, s));
       // poll the active count one step late so the stream never drains
@@ -935,6 +1028,10 @@ extern "C" hh_status hh_solve(hh_ctx* c, int32_t nrhs, const void* f, const void
   else
     st = stationary(c, q, b, reinterpret_cast<c128*>(u), rtol, maxit, nb, iters, relres, conv);
   if (st != HH_OK) return st;
+  if (c->prof) {
+    HH_TRY(sync(c));
+    prof_collect(c);
+  }
   bool all = true;
   for (int k = 0; k < q; ++k) {
     if (info) {
@@ -945,6 +1042,33 @@ extern "C" hh_status hh_solve(hh_ctx* c, int32_t nrhs, const void* f, const void
     all = all && conv[k];
   }
   if (!all) return fail(c, HH_ENOTCONV, "not converged within maxit");
+  return HH_OK;
+}
+
+extern "C" hh_status hh_profile(hh_ctx* c, int32_t enable) {
+  HH_TRY(check_usable(c));
+  HH_TRY(sync(c));
+  prof_collect(c);
+  c->prof = enable != 0;
+  for (int f = 0; f < 4; ++f) {
+    c->prof_ms[f] = 0.0;
+    c->prof_bytes[f] = 0.0;
+    c->prof_flops[f] = 0.0;
+    c->prof_n[f] = 0;
+  }
+  return HH_OK;
+}
+
+extern "C" hh_status hh_profile_read(hh_ctx* c, int32_t family, int64_t* launches, double* total_ms, double* bytes,
+                                     double* flops) {
+  HH_TRY(check_usable(c));
+  if (family < 0 || family > 3) return fail(c, HH_EINVAL, "unknown kernel family");
+  HH_TRY(sync(c));
+  prof_collect(c);
+  if (launches) *launches = c->prof_n[family];
+  if (total_ms) *total_ms = c->prof_ms[family];
+  if (bytes) *bytes = c->prof_bytes[family];
+  if (flops) *flops = c->prof_flops[family];
   return HH_OK;
 }
 

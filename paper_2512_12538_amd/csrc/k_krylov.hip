@@ -38,19 +38,26 @@ __device__ __forceinline__ double2 block_sum(double2 v, double* sx, double* sy) 
 }
 
 // partial[((k*q + b)*NB + blk] = sum over the block's chunk of conj(V_k[b]) W[b],
-// KG consecutive k per block so that W is read once per KG products.
+// KG consecutive k per block so that W is read once per KG products.  With
+// wnorm, the first group also accumulates |W[b]|^2 into row nk.  Columns with
+// skip[b] == 0 are left untouched (skip may be null).
 __global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, int NB, const c128* __restrict__ V,
                                                     long long vstride, const c128* __restrict__ W,
-                                                    c128* __restrict__ partial) {
+                                                    c128* __restrict__ partial, int wnorm,
+                                                    const int* __restrict__ skip) {
   const int blk = blockIdx.x, k0 = blockIdx.y * KG, b = blockIdx.z;
+  if (skip && !skip[b]) return;
   const long long per = (n + NB - 1) / NB;
   const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
   const c128* w = W + (long long)b * n;
+  const bool wn = wnorm && k0 == 0;
   double2 acc[KG];
+  double nw = 0.0;
 #pragma unroll
   for (int t = 0; t < KG; ++t) acc[t] = mk(0.0, 0.0);
   for (long long i = lo + threadIdx.x; i < hi; i += TB) {
     const double2 wv = w[i];
+    if (wn) nw += cabs2(wv);
 #pragma unroll
     for (int t = 0; t < KG; ++t)
       if (k0 + t < nk) acc[t] = cfmac(V[(k0 + t) * vstride + (long long)b * n + i], wv, acc[t]);
@@ -58,14 +65,21 @@ __global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, 
   __shared__ double sx[TB], sy[TB];
 #pragma unroll
   for (int t = 0; t < KG; ++t) {
+    if (k0 + t >= nk) break;
     const double2 r = block_sum(acc[t], sx, sy);
-    if (threadIdx.x == 0 && k0 + t < nk) partial[((long long)(k0 + t) * q + b) * NB + blk] = r;
+    if (threadIdx.x == 0) partial[((long long)(k0 + t) * q + b) * NB + blk] = r;
+  }
+  if (wn) {
+    const double2 r = block_sum(mk(nw, 0.0), sx, sy);
+    if (threadIdx.x == 0) partial[((long long)nk * q + b) * NB + blk] = r;
   }
 }
 
-__global__ void k_dot_final(int nkq, int NB, const c128* __restrict__ partial, c128* __restrict__ out) {
+__global__ void k_dot_final(int nkq, int q, int NB, const c128* __restrict__ partial, c128* __restrict__ out,
+                            const int* __restrict__ skip) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nkq) return;
+  if (skip && !skip[t % q]) return;
   double2 acc = mk(0.0, 0.0);
   for (int blk = 0; blk < NB; ++blk) acc = cadd(acc, partial[(long long)t * NB + blk]);
   out[t] = acc;
@@ -76,8 +90,10 @@ __global__ void k_dot_final(int nkq, int NB, const c128* __restrict__ partial, c
 // LDS; the k loop is unrolled by four so four basis loads are in flight.
 __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n, int NB, const c128* __restrict__ V,
                                                      long long vstride, const c128* __restrict__ h,
-                                                     c128* __restrict__ W, c128* __restrict__ npart) {
+                                                     c128* __restrict__ W, c128* __restrict__ npart,
+                                                     const int* __restrict__ skip) {
   const int blk = blockIdx.x, b = blockIdx.y;
+  if (skip && !skip[b]) return;
   __shared__ double2 hs[128];
   for (int k = threadIdx.x; k < nk; k += TB) hs[k] = h[k * q + b];
   __syncthreads();
@@ -105,6 +121,19 @@ __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n,
     const double2 r = block_sum(mk(nrm, 0.0), sx, sy);
     if (threadIdx.x == 0) npart[(long long)b * NB + blk] = r;
   }
+}
+
+// Second Gram-Schmidt pass wanted when the first one cancelled more than a
+// factor eta: |w'|^2 < eta^2 |w|^2 (w0n2 = |w|^2 before, w1n2 = |w'|^2 after).
+// Columns that skip it get h2 = 0 so that h1 + h2 stays the projection.
+__global__ void k_reorth_flag(int q, int nk, const c128* __restrict__ w0n2, const c128* __restrict__ w1n2, double eta2,
+                              int* __restrict__ need, c128* __restrict__ h2) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= q) return;
+  const int nd = eta2 >= 1.0 || w1n2[b].x < eta2 * w0n2[b].x;
+  need[b] = nd;
+  if (!nd)
+    for (int k = 0; k < nk; ++k) h2[k * q + b] = mk(0.0, 0.0);
 }
 
 __global__ void __launch_bounds__(TB) k_normalize(int q, long long n, const c128* __restrict__ nrm2,
@@ -221,23 +250,30 @@ inline int gx(long long n, int cap) {
 int multidot_nblocks(long long n) { return nblocks(n); }
 
 hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long vstride, const c128* W,
-                           c128* partial, c128* out, hipStream_t s) {
+                           c128* partial, c128* out, hipStream_t s, int wnorm, const int* skip) {
   if (nk <= 0 || q <= 0) return hipSuccess;
   const int NB = nblocks(n);
   hipLaunchKernelGGL(k_dot_partial, dim3(NB, (nk + KG - 1) / KG, q), dim3(TB), 0, s, nk, q, n, NB, V, vstride, W,
-                     partial);
-  const int nkq = nk * q;
-  hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, NB, partial, out);
+                     partial, wnorm, skip);
+  const int nkq = (nk + (wnorm ? 1 : 0)) * q;
+  hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, q, NB, partial, out, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h, c128* W,
-                               c128* partial, c128* nrm2, hipStream_t s) {
+                               c128* partial, c128* nrm2, hipStream_t s, const int* skip) {
   if (nk <= 0 || q <= 0) return hipSuccess;
   const int NB = nblocks(n);
   hipLaunchKernelGGL(k_basis_update, dim3(NB, q), dim3(TB), 0, s, nk, q, n, NB, V, vstride, h, W,
-                     nrm2 ? partial : nullptr);
-  if (nrm2) hipLaunchKernelGGL(k_dot_final, dim3((q + 127) / 128), dim3(128), 0, s, q, NB, partial, nrm2);
+                     nrm2 ? partial : nullptr, skip);
+  if (nrm2) hipLaunchKernelGGL(k_dot_final, dim3((q + 127) / 128), dim3(128), 0, s, q, q, NB, partial, nrm2, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_reorth_flag(int q, int nk, const c128* w0n2, const c128* w1n2, double eta, int* need, c128* h2,
+                              hipStream_t s) {
+  if (q <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reorth_flag, dim3((q + 127) / 128), dim3(128), 0, s, q, nk, w0n2, w1n2, eta * eta, need, h2);
   return hipGetLastError();
 }
 

@@ -83,13 +83,18 @@ hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, c
 
 // ---------------------------------------------------------------- Krylov (k_krylov.hip)
 int multidot_nblocks(long long n);
-// out[k*q + b] = sum_x conj(V_k[b][x]) W[b][x], k < nk (V_k at V + k*vstride); partial: nk*q*NB entries
+// out[k*q + b] = sum_x conj(V_k[b][x]) W[b][x], k < nk (V_k at V + k*vstride); with wnorm also
+// out[nk*q + b] = |W[b]|^2; columns with skip[b] == 0 untouched (skip may be null);
+// partial: (nk+1)*q*NB entries
 hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long vstride, const c128* W,
-                           c128* partial, c128* out, hipStream_t s);
+                           c128* partial, c128* out, hipStream_t s, int wnorm = 0, const int* skip = nullptr);
 // W[b] -= sum_k V_k[b] h[k*q + b]; if nrm2 is non-null also nrm2[b] = ||W[b]||^2 after the update
-// (partial: q*NB scratch entries)
+// (partial: q*NB scratch entries); columns with skip[b] == 0 untouched
 hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h, c128* W,
-                               c128* partial, c128* nrm2, hipStream_t s);
+                               c128* partial, c128* nrm2, hipStream_t s, const int* skip = nullptr);
+// need[b] = (w1n2[b] < eta^2 w0n2[b]) (always when eta >= 1); h2[:, b] = 0 where not needed
+hipError_t launch_reorth_flag(int q, int nk, const c128* w0n2, const c128* w1n2, double eta, int* need, c128* h2,
+                              hipStream_t s);
 // y[b] = x[b] / sqrt(re nrm2[b]) (zero if the norm is zero); nrm[b] = the norm
 hipError_t launch_normalize(int q, long long n, const c128* nrm2, const c128* x, c128* y, double* nrm,
                             hipStream_t s);

@@ -160,6 +160,28 @@ def test_full_size_2d_gmres_matches_oracle(hh):
         hh.hh_destroy(ctx)
 
 
+@pytest.mark.parametrize("full_reorth", [False, True])
+def test_gram_schmidt_variants_match_oracle(hh, full_reorth):
+    from gpu_util import build_both, dev, host, rel
+
+    N = 96
+    kk = np.full((N + 1) ** 2, 15.0)
+    ctx = hh.hh_setup(2, N, kk, hh.decomposition([(4, 4)], [4]), full_reorth=full_reorth)
+    S = HierarchicalORAS(2, N, kk, [(4, 4)], [4])
+    try:
+        build_both(hh, ctx, S, rank=4, oversample=6)
+        f = W.smoothed_gaussian_rhs(N, 41, 2)
+        u = dev(np.zeros_like(f))
+        info = hh.hh_solve(ctx, dev(f), u, rtol=1e-10, maxit=200)
+        assert all(i[1] for i in info)
+        for b in range(2):
+            uo, io = krylov.fgmres(lambda x: S.A @ x, S.precondition, f[b], tol=1e-10, maxit=200)
+            assert abs(info[b][0] - io.iters) <= 1
+            assert rel(host(u)[b], uo) < 1e-9
+    finally:
+        hh.hh_destroy(ctx)
+
+
 def test_batch_invariance(hh):
     from gpu_util import build_both, dev, host
 

@@ -36,6 +36,7 @@ def test_library_exports_every_declared_symbol():
 def test_binding_imports_and_rejects_bad_shapes_on_host():
     import paper_2512_12538_amd as hh
 
+    hh.load()
     d = hh.decomposition([(4, 4)], [4])
     assert d.levels == 1 and d.m[0][0] == 4 and d.overlap_cells[0] == 4
     assert hh.library_path() == LIB
