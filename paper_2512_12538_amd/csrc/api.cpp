@@ -64,6 +64,7 @@ struct Level {
   int qcap = 0;
   c128 *R = nullptr, *X = nullptr, *T = nullptr, *E = nullptr, *U = nullptr;
   c128 *cvec = nullptr, *yvec = nullptr;
+  c128* W = nullptr;  // leaf level: the two half-sweep end lines per box (2 nbox q max_ny)
 };
 
 }  // namespace
@@ -180,7 +181,7 @@ hh_status ensure_work(hh_ctx* c, int lo, int q) {
   for (int l = lo; l <= c->L; ++l) {
     Level& L = c->lv[l];
     if (L.qcap >= q) continue;
-    for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec}) {
+    for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec, &L.W}) {
       dfree(c, *b);
       *b = nullptr;
     }
@@ -194,6 +195,7 @@ hh_status ensure_work(hh_ctx* c, int lo, int q) {
       HH_TRY(dalloc(c, &L.cvec, (size_t)L.nc_total * q));
       HH_TRY(dalloc(c, &L.yvec, (size_t)L.nc_total * q));
     }
+    if (l == c->L) HH_TRY(dalloc(c, &L.W, (size_t)2 * L.nbox * L.max_ny * q));
     L.qcap = q;
   }
   return HH_OK;
@@ -309,9 +311,9 @@ hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x) {
     if (c->prof) leaf_solve_cost(Lv, q, c->precision == HH_MIXED ? 8 : 16, bytes, flops);
     ProfScope ps(c, 0, bytes, flops);
     if (c->precision == HH_MIXED) {
-      HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, c->stream));
+      HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, Lv.W, c->stream));
     } else {
-      HH_CHECK(launch_leaf_solve<double>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G, rhs, x, c->stream));
+      HH_CHECK(launch_leaf_solve<double>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G, rhs, x, Lv.W, c->stream));
     }
     return HH_OK;
   }
@@ -483,25 +485,31 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
   c->g_total = goff;
   for (int l = 0; l <= c->L; ++l)
     if ((st = push_boxes(c, c->lv[l])) != HH_OK) return bail(st);
-  // tail padding: the pipelined solve reads (masked) up to K*R rows past a line's end
+  // tail padding (zeroed): the sweeps read whole column slices and row groups past a line's end
   const long long gpad = 256LL * 256LL;
   if ((st = dalloc(c, &c->G, (size_t)(goff + gpad))) != HH_OK) return bail(st);
-  if ((st = dalloc(c, &c->d_info, (size_t)std::max(leaf.nbox, 4096))) != HH_OK) return bail(st);
+  if (launch_fill_zero(c->G + goff, gpad * (long long)sizeof(c128), c->stream) != hipSuccess)
+    return bail(device_fail(c, "fill", hipGetLastError()));
+  const int ninfo = 3 * leaf.nbox;
+  if ((st = dalloc(c, &c->d_info, (size_t)std::max(ninfo, 4096))) != HH_OK) return bail(st);
   if (launch_leaf_factor(c->op, leaf.d, leaf.nbox, leaf.max_ny, c->G, c->d_info, c->stream) != hipSuccess)
     return bail(device_fail(c, "leaf factor", hipGetLastError()));
-  std::vector<int> info(leaf.nbox);
-  if (hipMemcpyAsync(info.data(), c->d_info, leaf.nbox * sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
+  std::vector<int> info(ninfo);
+  if (hipMemcpyAsync(info.data(), c->d_info, ninfo * sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
           hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(device_fail(c, "leaf factor sync", hipGetLastError()));
-  for (int i = 0; i < leaf.nbox; ++i)
+  for (int i = 0; i < ninfo; ++i)
     if (info[i] != 0) {
-      c->err = "zero pivot in the factorisation of leaf " + std::to_string(i);
+      const int lf = i < 2 * leaf.nbox ? i / 2 : i - 2 * leaf.nbox;
+      c->err = "zero pivot in the factorisation of leaf " + std::to_string(lf);
       hh_destroy(c);
       return HH_ESINGULAR;
     }
   if (c->precision == HH_MIXED) {
     if ((st = dalloc(c, &c->G32, (size_t)(goff + gpad))) != HH_OK) return bail(st);
+    if (launch_fill_zero(c->G32 + goff, gpad * (long long)sizeof(c64), c->stream) != hipSuccess)
+      return bail(device_fail(c, "fill", hipGetLastError()));
     if (launch_f64_to_f32(c->G, c->G32, goff, c->stream) != hipSuccess)
       return bail(device_fail(c, "convert", hipGetLastError()));
     if (hipStreamSynchronize(c->stream) != hipSuccess) return bail(device_fail(c, "sync", hipGetLastError()));

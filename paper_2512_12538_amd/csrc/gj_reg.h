@@ -127,14 +127,16 @@ __device__ __forceinline__ void invert(double2 (&A)[RE], int n, const Layout& L,
   lds_barrier();
 }
 
-// The same elimination with the diagonal pivots, one barrier per step.  Wave 0
-// watches the pivot ratio: if some |a_kk| falls below ratio * max_{i>kk} |a_ik|
-// the result is discarded (returns false) and the caller repeats the
-// inversion with row interchanges.  On success sc.pos is the identity.
+// The same elimination with the diagonal pivots, one barrier per step.  The
+// pivot ratio is watched without a reduction: the thread holding a(i, kk),
+// i > kk, flags the step if ratio * |a_ik| > |a_kk|; a flagged inversion is
+// discarded (returns false) and the caller repeats it with row interchanges.
+// On success sc.pos is the identity.
 template <int NT, int RE>
 __device__ __forceinline__ bool invert_diag(double2 (&A)[RE], int n, const Layout& L, Scratch& sc, double ratio) {
   const int tid = threadIdx.x;
   if (tid == 0) sc.bad = 0;
+  const double r2 = ratio * ratio;
   for (int kk = 0; kk < n; ++kk) {
     const int bsel = kk & 1;
     if (L.act) {
@@ -150,16 +152,12 @@ __device__ __forceinline__ bool invert_diag(double2 (&A)[RE], int n, const Layou
     lds_barrier();
     const double2 pv = sc.colk[bsel][kk];
     const double pa = cabs2(pv);
-    if (tid < 64) {
-      double mx = 0.0;
-      for (int i = kk + 1 + tid; i < n; i += 64) mx = fmax(mx, cabs2(sc.colk[bsel][i]));
-      for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
-      if (tid == 0 && (!(pa > 0.0) || pa < ratio * ratio * mx)) sc.bad = 1;
-    }
+    if (tid == 0 && !(pa > 0.0)) sc.bad = 1;
     if (L.act) {
       const double2 inv = pa > 0.0 ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
       const bool is_k = L.i == kk;
       const double2 f = sc.colk[bsel][L.i];
+      if (L.i > kk && L.g == kk % L.G && !(r2 * cabs2(f) <= pa)) sc.bad = 1;
 #pragma unroll
       for (int r = 0; r < RE; ++r) {
         const int c = L.g + L.G * r;

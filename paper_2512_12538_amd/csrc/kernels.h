@@ -28,13 +28,18 @@ hipError_t launch_f64_to_f32(const c128* x, c64* y, long long n, hipStream_t s);
 hipError_t launch_rhs_with_impedance(const OpDev& op, const BoxDev* root, int q, const c128* f, const c128* g,
                                      c128* out, hipStream_t s);
 
-// ---------------------------------------------------------------- leaf solves (k_leaf.hip)
-// Block-tridiagonal factorisation of every leaf box: G_j = S_j^{-1} per grid line (FP64).
+// ---------------------------------------------------------------- leaf solves (k_leaf.hip, k_sweep.hip)
+// Two-ended block-tridiagonal factorisation of every leaf box (FP64): G_j per
+// grid line, chains from both ends to the middle line nx / 2.  info: 3 nleaf ints.
 hipError_t launch_leaf_factor(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, c128* G,
                               int* info, hipStream_t s);
+// x = A~^{-1} rhs for every leaf box and q columns (two launches).  rhs and x
+// are distinct level buffers; edge holds 2 nleaf * q * max_ny entries of work
+// space.  G (T = double: FP64 factors, float: complex64 copy) needs 65536
+// readable entries past its end.
 template <typename T>
 hipError_t launch_leaf_solve(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, int q,
-                             const typename cvec<T>::type* G, const c128* rhs, c128* x, hipStream_t s);
+                             const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge, hipStream_t s);
 
 // ---------------------------------------------------------------- interface map / rSVD (k_rsvd.hip)
 // buf[box][c][iface[t]] = vals[voff[box] + c*m_in + t] for c < (use_r ? r : s); buf pre-zeroed

@@ -75,6 +75,40 @@ def test_smoother_without_coarse_matches_oracle(hh, dim, N, m, ov):
         hh.hh_destroy(ctx)
 
 
+# ---------------------------------------------------------------- leaf sweep shapes
+# Leaf widths b = ny in every shape bucket of the sweep kernel (<= 8, 16, 40,
+# 72, 144, 256), boxes of two and three grid lines (the two-ended sweep with
+# an empty bottom half), zero overlap, and batches whose column count leaves
+# a ragged last chunk for every column-block width (1, 2 and 4 per group).
+@pytest.mark.parametrize("dim,N,m,ov,nrhs", [
+    (2, 8, [(8, 8)], [0], 3),      # 1-cell boxes: nx = ny = 2
+    (2, 12, [(6, 6)], [0], 2),     # nx = ny = 3
+    (2, 16, [(8, 8)], [2], 2),     # nx, ny in {4, 5}
+    (2, 30, [(3, 3)], [2], 2),     # b <= 16
+    (2, 60, [(2, 2)], [6], 2),     # b <= 40
+    (2, 100, [(2, 1)], [4], 2),    # b = 101
+    (2, 180, [(3, 1)], [4], 1),    # b = 181
+    (2, 200, [(4, 4)], [4], 9),    # b <= 72, 32 half-box units: 2 columns per group, ragged
+    (2, 200, [(4, 4)], [4], 33),   # 4 columns per group, ragged
+])
+def test_leaf_sweep_shapes_match_oracle(hh, dim, N, m, ov, nrhs):
+    from gpu_util import build_both, dev, host, rel
+
+    n = (N + 1) ** dim
+    k = np.random.default_rng(7).uniform(6, 12, n)
+    ctx = hh.hh_setup(dim, N, k, hh.decomposition(m, ov))
+    S = HierarchicalORAS(dim, N, k, m, ov)
+    try:
+        build_both(hh, ctx, S, rank=0, oversample=0)
+        r = W.white_rhs(n, 8, nrhs)
+        z = dev(np.zeros_like(r))
+        hh.hh_precondition(ctx, dev(r), z)
+        ref = np.stack([S.precondition(r[i]) for i in range(nrhs)])
+        assert rel(host(z), ref) < 1e-11
+    finally:
+        hh.hh_destroy(ctx)
+
+
 # ---------------------------------------------------------------- 1D, two subdomains, exact basis
 def test_1d_two_subdomains_one_step_exact(hh):
     from gpu_util import build_both, dev, host, rel
