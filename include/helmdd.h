@@ -24,7 +24,9 @@
  *   - Node (p, q), 0 <= p, q <= N, has index p*(N+1) + q (1D: index p).
  *   - Device pointers are HIP device memory owned by the caller; the library
  *     never frees them.  The context owns every internal allocation
- *     (factorisations, coarse bases, A_c^{-1}, work space) until hh_destroy.
+ *     (factorisations, coarse bases, A_c^{-1}, work space) until hh_destroy,
+ *     which returns it to a process-wide cache of device blocks that later
+ *     contexts reuse (hh_release_cached_memory frees the cache).
  *   - All device work is enqueued on hh_options.stream (null: the default
  *     stream).  Calls return after the work they started has completed,
  *     except where stated.  A context is used by one host thread at a time.
@@ -165,6 +167,13 @@ hh_status hh_profile_read(hh_ctx* c, int32_t family, int64_t* launches, double* 
                           double* flops);
 
 hh_status hh_destroy(hh_ctx* c);
+
+/* Frees the device blocks cached by the library on the current device (blocks
+ * released by destroyed contexts and by buffer regrowth); *bytes (if non-null)
+ * receives the amount freed.  The cache holds at most a quarter of the device
+ * memory, or HH_POOL_CAP_GB gigabytes when that environment variable is set
+ * (read at the first allocation on the device). */
+hh_status hh_release_cached_memory(int64_t* bytes);
 const char* hh_last_error(const hh_ctx* c);
 const char* hh_status_string(hh_status s);
 

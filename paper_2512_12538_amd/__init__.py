@@ -85,6 +85,7 @@ def _load():
         "hh_destroy": [P],
         "hh_profile": [P, i32],
         "hh_profile_read": [P, i32, P, P, P, P],
+        "hh_release_cached_memory": [P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -273,6 +274,15 @@ def hh_profile_read(ctx, family: int):
     _check(_lib.hh_profile_read(ctx, family, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(by), ctypes.byref(fl)),
            ctx)
     return n.value, ms.value, by.value, fl.value
+
+
+def hh_release_cached_memory() -> int:
+    """Frees the library's cache of device blocks on the current device; returns the bytes freed."""
+    n = ctypes.c_int64(0)
+    st = _lib.hh_release_cached_memory(ctypes.byref(n))
+    if st != 0:
+        raise RuntimeError(f"hh_release_cached_memory: {_status_name(st)}")
+    return int(n.value)
 
 
 def hh_destroy(ctx) -> None:

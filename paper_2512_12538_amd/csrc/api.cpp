@@ -17,6 +17,7 @@
 #include "../../include/helmdd.h"
 #include "geometry.h"
 #include "kernels.h"
+#include "pool.h"
 
 namespace {
 
@@ -106,7 +107,7 @@ struct hh_ctx {
   long long prof_n[4] = {0, 0, 0, 0};
   int* poll = nullptr;          // pinned host words polled by the outer loop
   hipEvent_t poll_ev[2] = {nullptr, nullptr};
-  std::vector<void*> allocs;
+  std::vector<DevBuf> allocs;
 };
 
 namespace {
@@ -138,22 +139,21 @@ template <typename T>
 hh_status dalloc(hh_ctx* c, T** p, size_t count) {
   *p = nullptr;
   if (count == 0) return HH_OK;
-  void* q = nullptr;
-  hipError_t e = hipMalloc(&q, count * sizeof(T));
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(c, HH_ENOMEM, "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
-  }
-  c->allocs.push_back(q);
+  const size_t bytes = count * sizeof(T);
+  void* q = devpool::acquire(bytes, c->stream);
+  if (!q) return fail(c, HH_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+  c->allocs.push_back(DevBuf{q, bytes});
   *p = reinterpret_cast<T*>(q);
   return HH_OK;
 }
 
+// Back to the pool; work already enqueued on the context stream may still use it.
 void dfree(hh_ctx* c, void* p) {
   if (!p) return;
-  auto it = std::find(c->allocs.begin(), c->allocs.end(), p);
-  if (it != c->allocs.end()) c->allocs.erase(it);
-  (void)hipFree(p);
+  auto it = std::find_if(c->allocs.begin(), c->allocs.end(), [p](const DevBuf& b) { return b.p == p; });
+  if (it == c->allocs.end()) return;
+  devpool::release(p, it->bytes, c->stream);
+  c->allocs.erase(it);
 }
 
 template <typename T>
@@ -382,9 +382,15 @@ hh_status hh_destroy(hh_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   if (c->poll) (void)hipHostFree(c->poll);
-  for (void* p : c->allocs) (void)hipFree(p);
+  for (const DevBuf& b : c->allocs) devpool::release(b.p, b.bytes, c->stream);
   c->allocs.clear();
   delete c;
+  return HH_OK;
+}
+
+hh_status hh_release_cached_memory(int64_t* bytes) {
+  const size_t n = devpool::trim();
+  if (bytes) *bytes = (int64_t)n;
   return HH_OK;
 }
 

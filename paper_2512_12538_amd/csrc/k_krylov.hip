@@ -21,26 +21,109 @@ inline int nblocks(long long n) {
   return (int)nb;
 }
 
-__device__ __forceinline__ double2 block_sum(double2 v, double* sx, double* sy) {
-  sx[threadIdx.x] = v.x;
-  sy[threadIdx.x] = v.y;
-  __syncthreads();
-  for (int st = TB / 2; st > 0; st >>= 1) {
-    if (threadIdx.x < st) {
-      sx[threadIdx.x] += sx[threadIdx.x + st];
-      sy[threadIdx.x] += sy[threadIdx.x + st];
-    }
-    __syncthreads();
+constexpr int EPT = CHUNK / TB;  // elements per thread and pass over a block's chunk
+
+// ---- wave reductions without LDS: gfx950 permlane32/permlane16 swaps for
+// lane bits 5 and 4, DPP for bits 0..3.
+__device__ __forceinline__ double dpp_d(double v, int ctrl_sel) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  switch (ctrl_sel) {
+    case 0:  // quad_perm [1, 0, 3, 2]: lane ^ 1
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0xb1, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0xb1, 0xf, 0xf, false);
+      break;
+    case 1:  // quad_perm [2, 3, 0, 1]: lane ^ 2
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x4e, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x4e, 0xf, 0xf, false);
+      break;
+    case 2:  // row_ror:4
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x124, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x124, 0xf, 0xf, false);
+      break;
+    default:  // row_ror:8
+      lo = __builtin_amdgcn_update_dpp(0, lo, 0x128, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_update_dpp(0, hi, 0x128, 0xf, 0xf, false);
+      break;
   }
-  const double2 r = mk(sx[0], sy[0]);
+  return __hiloint2double(hi, lo);
+}
+// lanes < 32: a(l) + a(l + 32); lanes >= 32: b(l - 32) + b(l)  (likewise across 16-lane halves)
+__device__ __forceinline__ double swapsum32(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double swapsum16(double a, double b) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(a), (unsigned)__double2loint(b), false,
+                                                   false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(a), (unsigned)__double2hiint(b), false,
+                                                   false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+// sum over the lanes that share bits 4 and 5 (bits 0..3 summed)
+// (halve0: even lanes keep v, odd lanes keep other, each summed with its partner's)
+__device__ __forceinline__ double sum16(double v, bool halve0, double other) {
+  if (halve0) {
+    const bool odd = threadIdx.x & 1;
+    const double keep = odd ? other : v, send = odd ? v : other;
+    v = keep + dpp_d(send, 0);
+  } else {
+    v += dpp_d(v, 0);
+  }
+  v += dpp_d(v, 1);
+  v += dpp_d(v, 2);
+  v += dpp_d(v, 3);
+  return v;
+}
+
+// Block sums of KG = 8 complex values per thread, in a fixed tree.  Lane bits
+// 5, 4 and 0 halve the eight values (lane keeps the half its bit selects), bits
+// 1..3 are summed by DPP; the four waves meet in LDS.  Thread t < 8 returns
+// the block sum of value t.
+__device__ __forceinline__ double2 block_sum8(double2 (&a)[KG], double2* red) {
+  double2 v4[4], v2[2];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) v4[t] = mk(swapsum32(a[t].x, a[t + 4].x), swapsum32(a[t].y, a[t + 4].y));
+#pragma unroll
+  for (int t = 0; t < 2; ++t) v2[t] = mk(swapsum16(v4[t].x, v4[t + 2].x), swapsum16(v4[t].y, v4[t + 2].y));
+  const double2 v = mk(sum16(v2[0].x, true, v2[1].x), sum16(v2[0].y, true, v2[1].y));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int t = ((lane >> 5) & 1) * 4 + ((lane >> 4) & 1) * 2 + (lane & 1);
+  if ((lane & 0xe) == 0) red[wave * KG + t] = v;
+  __syncthreads();
+  double2 r = mk(0.0, 0.0);
+  if (threadIdx.x < KG) {
+#pragma unroll
+    for (int w = 0; w < TB / 64; ++w) r = cadd(r, red[w * KG + threadIdx.x]);
+  }
+  __syncthreads();
+  return r;
+}
+
+// Block sum of one real value per thread; thread 0 returns it.
+__device__ __forceinline__ double block_sum1(double v, double* red) {
+  v = swapsum32(v, v);
+  v = swapsum16(v, v);
+  v = sum16(v, false, 0.0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < TB / 64; ++w) r += red[w];
+  }
   __syncthreads();
   return r;
 }
 
 // partial[((k*q + b)*NB + blk] = sum over the block's chunk of conj(V_k[b]) W[b],
-// KG consecutive k per block so that W is read once per KG products.  With
-// wnorm, the first group also accumulates |W[b]|^2 into row nk.  Columns with
-// skip[b] == 0 are left untouched (skip may be null).
+// KG consecutive k per block so that W is read once per KG products; each
+// thread keeps KG x EPT basis loads in flight.  With wnorm, the first group
+// also accumulates |W[b]|^2 into row nk.  Columns with skip[b] == 0 are left
+// untouched (skip may be null).
 __global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, int NB, const c128* __restrict__ V,
                                                     long long vstride, const c128* __restrict__ W,
                                                     c128* __restrict__ partial, int wnorm,
@@ -50,28 +133,43 @@ __global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, 
   const long long per = (n + NB - 1) / NB;
   const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
   const c128* w = W + (long long)b * n;
+  const c128* vb = V + (long long)b * n;
   const bool wn = wnorm && k0 == 0;
+  const int kn = nk - k0 < KG ? nk - k0 : KG;
   double2 acc[KG];
   double nw = 0.0;
 #pragma unroll
   for (int t = 0; t < KG; ++t) acc[t] = mk(0.0, 0.0);
-  for (long long i = lo + threadIdx.x; i < hi; i += TB) {
-    const double2 wv = w[i];
-    if (wn) nw += cabs2(wv);
+  for (long long i0 = lo; i0 < hi; i0 += CHUNK) {
+    double2 wv[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const long long i = i0 + threadIdx.x + (long long)e * TB;
+      wv[e] = i < hi ? w[i] : mk(0.0, 0.0);
+    }
+    double2 vv[KG][EPT];
 #pragma unroll
     for (int t = 0; t < KG; ++t)
-      if (k0 + t < nk) acc[t] = cfmac(V[(k0 + t) * vstride + (long long)b * n + i], wv, acc[t]);
-  }
-  __shared__ double sx[TB], sy[TB];
 #pragma unroll
-  for (int t = 0; t < KG; ++t) {
-    if (k0 + t >= nk) break;
-    const double2 r = block_sum(acc[t], sx, sy);
-    if (threadIdx.x == 0) partial[((long long)(k0 + t) * q + b) * NB + blk] = r;
+      for (int e = 0; e < EPT; ++e) {
+        const long long i = i0 + threadIdx.x + (long long)e * TB;
+        vv[t][e] = (t < kn && i < hi) ? vb[(k0 + t) * vstride + i] : mk(0.0, 0.0);
+      }
+#pragma unroll
+    for (int t = 0; t < KG; ++t)
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) acc[t] = cfmac(vv[t][e], wv[e], acc[t]);
+    if (wn) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) nw += cabs2(wv[e]);
+    }
   }
+  __shared__ double2 red[(TB / 64) * KG];
+  const double2 r = block_sum8(acc, red);
+  if (threadIdx.x < kn) partial[((long long)(k0 + threadIdx.x) * q + b) * NB + blk] = r;
   if (wn) {
-    const double2 r = block_sum(mk(nw, 0.0), sx, sy);
-    if (threadIdx.x == 0) partial[((long long)nk * q + b) * NB + blk] = r;
+    const double rn = block_sum1(nw, reinterpret_cast<double*>(red));
+    if (threadIdx.x == 0) partial[((long long)nk * q + b) * NB + blk] = mk(rn, 0.0);
   }
 }
 
@@ -86,40 +184,66 @@ __global__ void k_dot_final(int nkq, int q, int NB, const c128* __restrict__ par
 }
 
 // W[b] -= sum_k V_k[b] h[k*q + b]; optionally the block partial sums of |W[b]|^2
-// after the update (same chunking as the inner products).  Coefficients sit in
-// LDS; the k loop is unrolled by four so four basis loads are in flight.
+// after the update (same chunking as the inner products).  The coefficients
+// are uniform per work-group (scalar loads); eight basis vectors x EPT
+// elements are loaded per thread before they are applied.
 __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n, int NB, const c128* __restrict__ V,
                                                      long long vstride, const c128* __restrict__ h,
                                                      c128* __restrict__ W, c128* __restrict__ npart,
                                                      const int* __restrict__ skip) {
   const int blk = blockIdx.x, b = blockIdx.y;
   if (skip && !skip[b]) return;
-  __shared__ double2 hs[128];
-  for (int k = threadIdx.x; k < nk; k += TB) hs[k] = h[k * q + b];
-  __syncthreads();
   const long long per = (n + NB - 1) / NB;
   const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
   const c128* vb = V + (long long)b * n;
+  c128* wb = W + (long long)b * n;
   double nrm = 0.0;
-  for (long long i = lo + threadIdx.x; i < hi; i += TB) {
-    double2 w = W[(long long)b * n + i];
-    int k = 0;
-    for (; k + 4 <= nk; k += 4) {
-      const double2 v0 = vb[(k + 0) * vstride + i], v1 = vb[(k + 1) * vstride + i];
-      const double2 v2 = vb[(k + 2) * vstride + i], v3 = vb[(k + 3) * vstride + i];
-      w = csub(w, cmul(v0, hs[k + 0]));
-      w = csub(w, cmul(v1, hs[k + 1]));
-      w = csub(w, cmul(v2, hs[k + 2]));
-      w = csub(w, cmul(v3, hs[k + 3]));
+  for (long long i0 = lo; i0 < hi; i0 += CHUNK) {
+    double2 w[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const long long i = i0 + threadIdx.x + (long long)e * TB;
+      w[e] = i < hi ? wb[i] : mk(0.0, 0.0);
     }
-    for (; k < nk; ++k) w = csub(w, cmul(vb[k * vstride + i], hs[k]));
-    W[(long long)b * n + i] = w;
-    nrm += cabs2(w);
+    int k = 0;
+    for (; k + KG <= nk; k += KG) {
+      double2 vv[KG][EPT];
+#pragma unroll
+      for (int t = 0; t < KG; ++t)
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          const long long i = i0 + threadIdx.x + (long long)e * TB;
+          vv[t][e] = i < hi ? vb[(k + t) * vstride + i] : mk(0.0, 0.0);
+        }
+#pragma unroll
+      for (int t = 0; t < KG; ++t) {
+        const double2 hk = h[(k + t) * q + b];
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) w[e] = csub(w[e], cmul(vv[t][e], hk));
+      }
+    }
+    for (; k < nk; ++k) {
+      const double2 hk = h[k * q + b];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const long long i = i0 + threadIdx.x + (long long)e * TB;
+        const double2 v = i < hi ? vb[k * vstride + i] : mk(0.0, 0.0);
+        w[e] = csub(w[e], cmul(v, hk));
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const long long i = i0 + threadIdx.x + (long long)e * TB;
+      if (i < hi) {
+        wb[i] = w[e];
+        nrm += cabs2(w[e]);
+      }
+    }
   }
   if (npart) {
-    __shared__ double sx[TB], sy[TB];
-    const double2 r = block_sum(mk(nrm, 0.0), sx, sy);
-    if (threadIdx.x == 0) npart[(long long)b * NB + blk] = r;
+    __shared__ double red[TB / 64];
+    const double r = block_sum1(nrm, red);
+    if (threadIdx.x == 0) npart[(long long)b * NB + blk] = mk(r, 0.0);
   }
 }
 

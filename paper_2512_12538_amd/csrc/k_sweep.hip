@@ -214,8 +214,7 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const int k = ks * R + r;
-        const CT v = Gj[(long long)k * b + rgi + RG * tm];
-        g[tm * R + r] = k < b ? v : zero;
+        g[tm * R + r] = Gj[(long long)k * b + rgi + RG * tm];
       }
   }
   for (int e = tid; e < 2 * KS * YS; e += NT) (&ybuf[0][0])[e] = zero;
@@ -255,6 +254,11 @@ __global__ void __launch_bounds__(64 * NW)
 #pragma unroll
       for (int t = 0; t < MF; ++t) pre[t] = src[oaddr[t] + loff];
     }
+    // issued here, consumed in the epilogue: kept ahead of the next line's G
+    // loads so that waiting for them leaves those in flight
+    __builtin_amdgcn_sched_barrier(0);
+    // y rows k >= b are zero in LDS, so the G entries read past a line's b
+    // columns (finite: the next columns, or the zeroed tail) add nothing
     const CT* Gn = Gl + (long long)jn * bb;
     const CT* Gc = Gl + (long long)j * bb;
     const CT* ys = &ybuf[s & 1][ks * YS];
@@ -272,8 +276,7 @@ __global__ void __launch_bounds__(64 * NW)
         if constexpr (PF) {
 #pragma unroll
           for (int c = 0; c < QB; ++c) acc[tm * QB + c] = cfma(g[tm * R + r], yv[c], acc[tm * QB + c]);
-          const CT v = Gn[(long long)k * b + rgi + RG * tm];
-          g[tm * R + r] = k < b ? v : zero;
+          g[tm * R + r] = Gn[(long long)k * b + rgi + RG * tm];
         } else {
           const CT v = Gc[(long long)k * b + rgi + RG * tm];
           const CT gv = k < b ? v : zero;

@@ -305,3 +305,28 @@ def test_invalid_arguments_rejected(hh):
     assert e.value.status == 1
     with pytest.raises(hh.HelmddError):
         hh.hh_setup(2, 32, float("nan"), hh.decomposition([(2, 2)], [4]))
+
+
+# ---------------------------------------------------------------- cached device memory
+def test_recreated_context_reuses_cached_memory_with_identical_results(hh):
+    """Contexts take their buffers from the library's device cache; a context
+    built on recycled blocks (stale contents) must give the same bits."""
+    from gpu_util import build_both, dev, host
+
+    N, m, ov = 40, [(2, 2)], [4]
+    k = np.full((N + 1) ** 2, 9.0)
+    f = W.smoothed_gaussian_rhs(N, 31, 2)
+    outs = []
+    for _ in range(2):
+        ctx = hh.hh_setup(2, N, k, hh.decomposition(m, ov))
+        S = HierarchicalORAS(2, N, k, m, ov)
+        try:
+            build_both(hh, ctx, S, rank=3, oversample=4)
+            u = dev(np.zeros_like(f))
+            hh.hh_solve(ctx, dev(f), u, rtol=1e-9, maxit=80)
+            outs.append(host(u))
+        finally:
+            hh.hh_destroy(ctx)
+    assert np.array_equal(outs[0], outs[1])
+    assert hh.hh_release_cached_memory() > 0
+    assert hh.hh_release_cached_memory() == 0
