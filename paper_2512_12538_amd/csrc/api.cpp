@@ -65,7 +65,9 @@ struct Level {
   int qcap = 0;
   c128 *R = nullptr, *X = nullptr, *T = nullptr, *E = nullptr, *U = nullptr;
   c128 *cvec = nullptr, *yvec = nullptr;
-  c128* W = nullptr;  // leaf level: the two half-sweep end lines per box (2 nbox q max_ny)
+  c128* W = nullptr;   // leaf level: the two half-sweep end lines per box (2 nbox q max_ny)
+  c128* RP = nullptr;  // parent levels: chunk partial sums of the coarse restriction
+  long long rp_len = 0;
 };
 
 }  // namespace
@@ -181,7 +183,7 @@ hh_status ensure_work(hh_ctx* c, int lo, int q) {
   for (int l = lo; l <= c->L; ++l) {
     Level& L = c->lv[l];
     if (L.qcap >= q) continue;
-    for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec, &L.W}) {
+    for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec, &L.W, &L.RP}) {
       dfree(c, *b);
       *b = nullptr;
     }
@@ -196,6 +198,11 @@ hh_status ensure_work(hh_ctx* c, int lo, int q) {
       HH_TRY(dalloc(c, &L.yvec, (size_t)L.nc_total * q));
     }
     if (l == c->L) HH_TRY(dalloc(c, &L.W, (size_t)2 * L.nbox * L.max_ny * q));
+    if (l < c->L) {
+      const Level& Ch = c->lv[l + 1];
+      L.rp_len = restrict_workspace(Ch.nbox, Ch.max_own, std::max(Ch.rmax, 1), q);
+      HH_TRY(dalloc(c, &L.RP, (size_t)L.rp_len));
+    }
     L.qcap = q;
   }
   return HH_OK;
@@ -295,7 +302,10 @@ hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
   HH_CHECK(launch_scatter_owned(Ch.d, Ch.nbox, Ch.max_own, P.d, q, Ch.X, out, c->stream));
   if (P.has_coarse) {
     HH_CHECK(launch_apply_box(c->op, P.d, P.nbox, P.max_n, q, out, r, P.T, 1, c->stream));
-    HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, P.d, P.dp, Ch.rmax, q, Ch.C, P.T, P.cvec, c->stream));
+    if (P.rp_len < restrict_workspace(Ch.nbox, Ch.max_own, Ch.rmax, q))
+      return fail(c, HH_EDEVICE, "coarse restriction workspace smaller than the launch needs");
+    HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, Ch.max_own, P.d, P.dp, Ch.rmax, q, Ch.C, P.T, P.RP, P.cvec,
+                                    c->stream));
     HH_CHECK(launch_coarse_gemv(P.dp, P.nbox, P.max_nc, q, P.Ainv, P.cvec, P.yvec, c->stream));
     HH_CHECK(launch_coarse_prolong(Ch.d, Ch.nbox, Ch.max_own, P.d, P.dp, q, Ch.C, P.yvec, out, c->stream));
   }
@@ -310,6 +320,7 @@ hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x) {
     double bytes = 0.0, flops = 0.0;
     if (c->prof) leaf_solve_cost(Lv, q, c->precision == HH_MIXED ? 8 : 16, bytes, flops);
     ProfScope ps(c, 0, bytes, flops);
+    if (Lv.qcap < q) return fail(c, HH_EDEVICE, "leaf solve work space smaller than the launch needs");
     if (c->precision == HH_MIXED) {
       HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, Lv.W, c->stream));
     } else {

@@ -178,127 +178,175 @@ __global__ void __launch_bounds__(TB) k_gj_unperm(const ParentDev* __restrict__ 
   }
 }
 
-// cvec[par][b][cidx + k] = C_child[k]^H t[par][b][owned nodes of child];
-// block (child, group of KC columns, chunk of QC right-hand sides), so C is
-// read q/QC times and t r/KC times.
-constexpr int KC = 4, QC = 8;
+// ---- the coarse products as FP64 matrix-core (MFMA 16x16x4) products.
+// Operand layouts of v_mfma_f64_16x16x4f64 (one wave): lane l holds
+// A[l & 15][l >> 4] and B[l >> 4][l & 15]; D[4 s + (l >> 4)][l & 15] is slot s
+// of lane l.  A complex product takes four real products on (re, im) parts.
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(TB) k_coarse_restrict(const BoxDev* __restrict__ child,
-                                                        const BoxDev* __restrict__ par,
-                                                        const ParentDev* __restrict__ pd, int kgroups, int q,
-                                                        const c128* __restrict__ C, const c128* __restrict__ t,
-                                                        c128* __restrict__ cvec) {
-  const int box = blockIdx.x / kgroups, k0 = (blockIdx.x % kgroups) * KC;
-  const int b0 = blockIdx.y * QC;
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// (re, im) += a * b
+__device__ __forceinline__ void cmfma(double2 a, double2 b, d4& re, d4& im) {
+  re = mfma(a.x, b.x, re);
+  re = mfma(-a.y, b.y, re);
+  im = mfma(a.x, b.y, im);
+  im = mfma(a.y, b.x, im);
+}
+// (re, im) += conj(a) * b
+__device__ __forceinline__ void cmfma_ca(double2 a, double2 b, d4& re, d4& im) {
+  re = mfma(a.x, b.x, re);
+  re = mfma(a.y, b.y, re);
+  im = mfma(a.x, b.y, im);
+  im = mfma(-a.y, b.x, im);
+}
+
+// parent-local index of owned node e of child B
+__device__ __forceinline__ long long owned_to_parent(const BoxDev& B, const BoxDev& P, int e) {
+  const int oa = e / B.own_ny, oc = e - oa * B.own_ny;
+  return (long long)(B.op0 + oa - P.p0) * P.ny + (B.oq0 + oc - P.q0);
+}
+
+constexpr int RCH = 256;  // owned nodes per restrict work-group (split of the inner dimension)
+
+// part[box][chunk][a][c] = sum over the chunk's owned nodes e of conj(C[e][a]) t[c][e]
+// (a < MT 16 padded, c < q padded to 64).  Wave w: right-hand sides 16 w .. 16 w + 15
+// of the work-group's 64; MT tiles of 16 coarse vectors.
+template <int MT>
+__global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
+                                                      int nchunk, int q, int qpad, const c128* __restrict__ C,
+                                                      const c128* __restrict__ t, c128* __restrict__ part) {
+  const int box = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
   const BoxDev B = child[box];
-  if (k0 >= B.r) return;
+  const int e0 = chunk * RCH;
+  if (B.r == 0 || e0 >= B.n_own) return;
   const BoxDev P = par[B.parent];
-  const ParentDev D = pd[B.parent];
-  double2 acc[KC][QC];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int m = lane & 15, kk = lane >> 4;
+  const int c = blockIdx.y * 64 + wave * 16 + m;
+  const int e1 = e0 + RCH < B.n_own ? e0 + RCH : B.n_own;
+  const c128* tb = t + P.voff * q + (long long)(c < q ? c : 0) * P.n;
+  const c128* Cb = C + B.coff;
+  d4 re[MT], im[MT];
 #pragma unroll
-  for (int a = 0; a < KC; ++a)
+  for (int mt = 0; mt < MT; ++mt) re[mt] = im[mt] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = e0; k0 < e1; k0 += 4) {
+    const int e = k0 + kk;
+    const bool ve = e < e1;
+    const double2 tv = (ve && c < q) ? tb[owned_to_parent(B, P, e)] : mk(0.0, 0.0);
 #pragma unroll
-    for (int c = 0; c < QC; ++c) acc[a][c] = mk(0.0, 0.0);
-  for (int e = threadIdx.x; e < B.n_own; e += TB) {
-    const int oa = e / B.own_ny, oc = e - oa * B.own_ny;
-    const long long pl = (long long)(B.op0 + oa - P.p0) * P.ny + (B.oq0 + oc - P.q0);
-    double2 cv[KC];
-#pragma unroll
-    for (int a = 0; a < KC; ++a)
-      cv[a] = k0 + a < B.r ? C[B.coff + (long long)(k0 + a) * B.n_own + e] : mk(0.0, 0.0);
-#pragma unroll
-    for (int c = 0; c < QC; ++c) {
-      if (b0 + c < q) {
-        const double2 tv = t[P.voff * q + (long long)(b0 + c) * P.n + pl];
-#pragma unroll
-        for (int a = 0; a < KC; ++a) acc[a][c] = cfmac(cv[a], tv, acc[a][c]);
-      }
+    for (int mt = 0; mt < MT; ++mt) {
+      const int a = mt * 16 + m;
+      const double2 cv = (ve && a < B.r) ? Cb[(long long)a * B.n_own + e] : mk(0.0, 0.0);
+      cmfma_ca(cv, tv, re[mt], im[mt]);
     }
   }
-  __shared__ double sx[TB], sy[TB];
+  c128* pb = part + ((long long)box * nchunk + chunk) * (MT * 16) * qpad;
+  const int cc = blockIdx.y * 64 + wave * 16 + (lane & 15);
 #pragma unroll
-  for (int a = 0; a < KC; ++a)
+  for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int c = 0; c < QC; ++c) {
-      sx[threadIdx.x] = acc[a][c].x;
-      sy[threadIdx.x] = acc[a][c].y;
-      __syncthreads();
-      for (int st = TB / 2; st > 0; st >>= 1) {
-        if (threadIdx.x < st) {
-          sx[threadIdx.x] += sx[threadIdx.x + st];
-          sy[threadIdx.x] += sy[threadIdx.x + st];
-        }
-        __syncthreads();
-      }
-      if (threadIdx.x == 0 && k0 + a < B.r && b0 + c < q)
-        cvec[D.yoff * q + (long long)(b0 + c) * D.n_c + B.cidx + k0 + a] = mk(sx[0], sy[0]);
-      __syncthreads();
+    for (int sl = 0; sl < 4; ++sl) {
+      const int a = mt * 16 + 4 * sl + (lane >> 4);
+      pb[(long long)a * qpad + cc] = mk(re[mt][sl], im[mt][sl]);
     }
 }
 
-// y[par][b] = A_c^{-1} cvec[par][b]: block (64 rows, parent, rhs), four column
-// slices per row reduced in LDS.
-__global__ void __launch_bounds__(TB) k_coarse_gemv(const ParentDev* __restrict__ pd, int q,
+// cvec[par][c][cidx + a] = sum over chunks (in order) of part[box][chunk][a][c]
+__global__ void __launch_bounds__(TB) k_restrict_sum(const BoxDev* __restrict__ child,
+                                                     const ParentDev* __restrict__ pd, int nchunk, int rpad, int q,
+                                                     int qpad, const c128* __restrict__ part, c128* __restrict__ cvec) {
+  const int box = blockIdx.y;
+  const BoxDev B = child[box];
+  const int idx = blockIdx.x * TB + threadIdx.x;
+  const int a = idx / q, c = idx - a * q;
+  if (a >= B.r) return;
+  const ParentDev D = pd[B.parent];
+  const int nch = (B.n_own + RCH - 1) / RCH;
+  const c128* pb = part + (long long)box * nchunk * rpad * qpad + (long long)a * qpad + c;
+  double2 s = mk(0.0, 0.0);
+  for (int ch = 0; ch < nch; ++ch) s = cadd(s, pb[(long long)ch * rpad * qpad]);
+  cvec[D.yoff * q + (long long)c * D.n_c + B.cidx + a] = s;
+}
+
+// y[par][c] = A_c^{-1} cvec[par][c]: one wave per 16 x 16 output tile (rows of
+// A_c^{-1} x right-hand sides), inner dimension n_c in steps of four.
+__global__ void __launch_bounds__(TB) k_coarse_gemm(const ParentDev* __restrict__ pd, int q, int mtiles, int ntiles,
                                                     const c128* __restrict__ Ainv, const c128* __restrict__ cvec,
                                                     c128* __restrict__ y) {
-  const int pb = blockIdx.y / q, col = blockIdx.y % q;
+  const int pb = blockIdx.y;
   const ParentDev D = pd[pb];
   const int n = D.n_c;
-  const int r0 = blockIdx.x * 64;
-  if (r0 >= n) return;
-  const c128* cv = cvec + D.yoff * q + (long long)col * n;
+  const int tile = blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
+  if (tile >= mtiles * ntiles) return;
+  const int mt = tile / ntiles, nt = tile - mt * ntiles;
+  if (mt * 16 >= n) return;
+  const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+  const int row = mt * 16 + m, col = nt * 16 + m;
   const c128* A = Ainv + D.aoff;
-  const int rr = threadIdx.x & 63, sl = threadIdx.x >> 6;
-  const int r = r0 + rr;
-  double2 acc = mk(0.0, 0.0);
-  if (r < n)
-    for (int c = sl; c < n; c += 4) acc = cfma(A[r + (long long)c * n], cv[c], acc);
-  __shared__ double2 red[4][64];
-  red[sl][rr] = acc;
-  __syncthreads();
-  if (sl == 0 && r < n) {
-    const double2 s = cadd(cadd(red[0][rr], red[1][rr]), cadd(red[2][rr], red[3][rr]));
-    y[D.yoff * q + (long long)col * n + r] = s;
+  const c128* cv = cvec + D.yoff * q;
+  d4 re = {0.0, 0.0, 0.0, 0.0}, im = re;
+  for (int k0 = 0; k0 < n; k0 += 4) {
+    const int k = k0 + kk;
+    const double2 av = (row < n && k < n) ? A[row + (long long)k * n] : mk(0.0, 0.0);
+    const double2 bv = (k < n && col < q) ? cv[(long long)col * n + k] : mk(0.0, 0.0);
+    cmfma(av, bv, re, im);
+  }
+  const int cc = nt * 16 + (lane & 15);
+  if (cc < q) {
+#pragma unroll
+    for (int sl = 0; sl < 4; ++sl) {
+      const int r = mt * 16 + 4 * sl + (lane >> 4);
+      if (r < n) y[D.yoff * q + (long long)cc * n + r] = mk(re[sl], im[sl]);
+    }
   }
 }
 
-// u[par][b][owned nodes of child] += C_child y: one thread per owned node, QC
-// right-hand sides per thread so C is read q/QC times.
-__global__ void __launch_bounds__(TB) k_coarse_prolong(const BoxDev* __restrict__ child,
-                                                       const BoxDev* __restrict__ par,
-                                                       const ParentDev* __restrict__ pd, int q,
-                                                       const c128* __restrict__ C, const c128* __restrict__ y,
-                                                       c128* __restrict__ u) {
-  const int box = blockIdx.y;
-  const int b0 = blockIdx.z * QC;
+// u[par][c][owned nodes of child] += C_child y: computed transposed,
+// (y^T C^T)[c][e], so that a wave's D tile spans 16 consecutive owned nodes.
+// Wave: 16 nodes x 64 right-hand sides (four tiles); inner dimension r.
+__global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
+                                                     const ParentDev* __restrict__ pd, int ngroups, int q,
+                                                     const c128* __restrict__ C, const c128* __restrict__ y,
+                                                     c128* __restrict__ u) {
+  const int box = blockIdx.x / ngroups;
   const BoxDev B = child[box];
-  if (B.r == 0) return;
+  const int e0 = ((blockIdx.x % ngroups) * (TB / 64) + (threadIdx.x >> 6)) * 16;
+  if (B.r == 0 || e0 >= B.n_own) return;
   const BoxDev P = par[B.parent];
   const ParentDev D = pd[B.parent];
-  __shared__ double2 ys[QC][128];
-  for (int e = threadIdx.x; e < QC * B.r; e += TB) {
-    const int c = e / B.r, k = e % B.r;
-    ys[c][k] = b0 + c < q ? y[D.yoff * q + (long long)(b0 + c) * D.n_c + B.cidx + k] : mk(0.0, 0.0);
+  const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+  const int c0 = blockIdx.y * 64;
+  const c128* yb = y + D.yoff * q + B.cidx;
+  const c128* Cb = C + B.coff;
+  const int en = e0 + m;
+  d4 re[4], im[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) re[t] = im[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < B.r; k0 += 4) {
+    const int a = k0 + kk;
+    const double2 cv = (a < B.r && en < B.n_own) ? Cb[(long long)a * B.n_own + en] : mk(0.0, 0.0);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = c0 + 16 * t + m;
+      const double2 yv = (a < B.r && c < q) ? yb[(long long)c * D.n_c + a] : mk(0.0, 0.0);
+      cmfma(yv, cv, re[t], im[t]);
+    }
   }
-  __syncthreads();
-  for (int e = blockIdx.x * TB + threadIdx.x; e < B.n_own; e += gridDim.x * TB) {
-    double2 acc[QC];
+  const int e = e0 + (lane & 15);
+  if (e < B.n_own) {
+    const long long pl = owned_to_parent(B, P, e);
 #pragma unroll
-    for (int c = 0; c < QC; ++c) acc[c] = mk(0.0, 0.0);
-    for (int k = 0; k < B.r; ++k) {
-      const double2 cv = C[B.coff + (long long)k * B.n_own + e];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-      for (int c = 0; c < QC; ++c) acc[c] = cfma(cv, ys[c][k], acc[c]);
-    }
-    const int oa = e / B.own_ny, oc = e - oa * B.own_ny;
-    const long long pl = (long long)(B.op0 + oa - P.p0) * P.ny + (B.oq0 + oc - P.q0);
-#pragma unroll
-    for (int c = 0; c < QC; ++c) {
-      if (b0 + c < q) {
-        c128* uv = u + P.voff * q + (long long)(b0 + c) * P.n;
-        uv[pl] = cadd(uv[pl], acc[c]);
+      for (int sl = 0; sl < 4; ++sl) {
+        const int c = c0 + 16 * t + 4 * sl + (lane >> 4);
+        if (c < q) {
+          c128* uv = u + P.voff * q + (long long)c * P.n + pl;
+          *uv = cadd(*uv, mk(re[t][sl], im[t][sl]));
+        }
       }
-    }
   }
 }
 
@@ -341,19 +389,46 @@ hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* 
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const BoxDev* par, const ParentDev* pd,
-                                  int rmax, int q, const c128* C, const c128* t, c128* cvec, hipStream_t s) {
+namespace {
+// tiles of 16 coarse vectors instantiated for the restriction: 2, 4 or 8 (0: unsupported)
+int restrict_tiles(int rmax) {
+  const int mt = (rmax + 15) / 16;
+  return mt <= 2 ? 2 : mt <= 4 ? 4 : mt <= 8 ? 8 : 0;
+}
+}  // namespace
+
+// The workspace holds, per child and chunk, the full padded (16 MT) x (q
+// rounded up to 64) tile that k_restrict_mfma writes.
+long long restrict_workspace(int nchild, int max_own, int rmax, int q) {
+  if (nchild <= 0 || rmax <= 0 || q <= 0) return 0;
+  const long long nchunk = (max_own + RCH - 1) / RCH;
+  const long long rpad = 16LL * restrict_tiles(rmax), qpad = (q + 63) / 64 * 64;
+  return nchild * nchunk * rpad * qpad;
+}
+
+hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
+                                  const ParentDev* pd, int rmax, int q, const c128* C, const c128* t, c128* part,
+                                  c128* cvec, hipStream_t s) {
   if (nchild <= 0 || rmax <= 0 || q <= 0) return hipSuccess;
-  const int kgroups = (rmax + KC - 1) / KC;
-  hipLaunchKernelGGL(k_coarse_restrict, dim3(nchild * kgroups, (q + QC - 1) / QC), dim3(TB), 0, s, child, par, pd,
-                     kgroups, q, C, t, cvec);
+  const int mt = restrict_tiles(rmax);
+  if (mt == 0) return hipErrorInvalidValue;
+  const int nchunk = (max_own + RCH - 1) / RCH, qpad = (q + 63) / 64 * 64;
+  const dim3 grid(nchild * nchunk, qpad / 64);
+  if (mt == 2) hipLaunchKernelGGL(k_restrict_mfma<2>, grid, dim3(TB), 0, s, child, par, nchunk, q, qpad, C, t, part);
+  else if (mt == 4) hipLaunchKernelGGL(k_restrict_mfma<4>, grid, dim3(TB), 0, s, child, par, nchunk, q, qpad, C, t, part);
+  else hipLaunchKernelGGL(k_restrict_mfma<8>, grid, dim3(TB), 0, s, child, par, nchunk, q, qpad, C, t, part);
+  hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + TB - 1) / TB, nchild), dim3(TB), 0, s, child, pd, nchunk,
+                     16 * mt, q, qpad, part, cvec);
   return hipGetLastError();
 }
 
 hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, const c128* Ainv,
                               const c128* cvec, c128* y, hipStream_t s) {
   if (npar <= 0 || max_nc <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_gemv, dim3((max_nc + 63) / 64, npar * q), dim3(TB), 0, s, pd, q, Ainv, cvec, y);
+  const int mtiles = (max_nc + 15) / 16, ntiles = (q + 15) / 16;
+  const int tiles = mtiles * ntiles;
+  hipLaunchKernelGGL(k_coarse_gemm, dim3((tiles + 3) / 4, npar), dim3(TB), 0, s, pd, q, mtiles, ntiles, Ainv, cvec,
+                     y);
   return hipGetLastError();
 }
 
@@ -361,7 +436,8 @@ hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, c
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
                                  hipStream_t s) {
   if (nchild <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_coarse_prolong, dim3(gx(max_own, 256), nchild, (q + QC - 1) / QC), dim3(TB), 0, s, child,
-                     par, pd, q, C, y, u);
+  const int ngroups = (max_own + 63) / 64;
+  hipLaunchKernelGGL(k_prolong_mfma, dim3(nchild * ngroups, (q + 63) / 64), dim3(TB), 0, s, child, par, pd, ngroups,
+                     q, C, y, u);
   return hipGetLastError();
 }

@@ -78,10 +78,17 @@ hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, co
 // npar*max_nc entries; info[p] = first zero pivot + 1 (0 if none)
 hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, c128* fcol, int* info,
                              hipStream_t s);
-hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const BoxDev* par, const ParentDev* pd,
-                                  int rmax, int q, const c128* C, const c128* t, c128* cvec, hipStream_t s);
+// cvec[par][c][cidx + a] = C_child[a]^H t[par][c][owned nodes of child]: FP64
+// matrix-core products over chunks of owned nodes into `part`
+// (restrict_workspace entries), then an ordered sum over the chunks.
+long long restrict_workspace(int nchild, int max_own, int rmax, int q);
+hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
+                                  const ParentDev* pd, int rmax, int q, const c128* C, const c128* t, c128* part,
+                                  c128* cvec, hipStream_t s);
+// y[par][c] = A_c^{-1} cvec[par][c] (FP64 matrix cores)
 hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, const c128* Ainv,
                               const c128* cvec, c128* y, hipStream_t s);
+// u[par][c][owned nodes of child] += C_child y[par][c][cidx ..] (FP64 matrix cores)
 hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
                                  hipStream_t s);
