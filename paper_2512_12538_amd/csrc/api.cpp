@@ -291,15 +291,22 @@ void leaf_solve_cost(const Level& L, int q, size_t gbytes, double& bytes, double
 
 // ------------------------------------------------------------------ the sweeps
 hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x);
+hh_status leaf_solve(hh_ctx* c, int q, const c128* rhs, c128* x, const BoxDev* par, c128* out);
 
 // out = B_l(r) for every box of level l: smoother over the children, then the
 // coarse correction of each box's own coarse space (eqs. (sub1)-(coarse1)).
+// Leaf children read R_i r from the parent vector and write P_i x into it
+// directly; inner levels go through their own level buffers.
 hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
   Level& P = c->lv[l];
   Level& Ch = c->lv[l + 1];
-  HH_CHECK(launch_gather_children(Ch.d, Ch.nbox, Ch.max_n, P.d, q, r, Ch.R, c->stream));
-  HH_TRY(solve_level(c, l + 1, q, Ch.R, Ch.X));
-  HH_CHECK(launch_scatter_owned(Ch.d, Ch.nbox, Ch.max_own, P.d, q, Ch.X, out, c->stream));
+  if (l + 1 == c->L) {
+    HH_TRY(leaf_solve(c, q, r, Ch.X, P.d, out));
+  } else {
+    HH_CHECK(launch_gather_children(Ch.d, Ch.nbox, Ch.max_n, P.d, q, r, Ch.R, c->stream));
+    HH_TRY(solve_level(c, l + 1, q, Ch.R, Ch.X));
+    HH_CHECK(launch_scatter_owned(Ch.d, Ch.nbox, Ch.max_own, P.d, q, Ch.X, out, c->stream));
+  }
   if (P.has_coarse) {
     HH_CHECK(launch_apply_box(c->op, P.d, P.nbox, P.max_n, q, out, r, P.T, 1, c->stream));
     if (P.rp_len < restrict_workspace(Ch.nbox, Ch.max_own, Ch.rmax, q))
@@ -307,7 +314,25 @@ hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
     HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, Ch.max_own, P.d, P.dp, Ch.rmax, q, Ch.C, P.T, P.RP, P.cvec,
                                     c->stream));
     HH_CHECK(launch_coarse_gemv(P.dp, P.nbox, P.max_nc, q, P.Ainv, P.cvec, P.yvec, c->stream));
-    HH_CHECK(launch_coarse_prolong(Ch.d, Ch.nbox, Ch.max_own, P.d, P.dp, q, Ch.C, P.yvec, out, c->stream));
+    HH_CHECK(launch_coarse_prolong(Ch.d, Ch.nbox, Ch.max_own, Ch.rmax, P.d, P.dp, q, Ch.C, P.yvec, out, c->stream));
+  }
+  return HH_OK;
+}
+
+// Exact solves of every leaf box (the local problems of eq. (sub1)); see
+// launch_leaf_solve for the in-place parent mode (par, out).
+hh_status leaf_solve(hh_ctx* c, int q, const c128* rhs, c128* x, const BoxDev* par, c128* out) {
+  Level& Lv = c->lv[c->L];
+  double bytes = 0.0, flops = 0.0;
+  if (c->prof) leaf_solve_cost(Lv, q, c->precision == HH_MIXED ? 8 : 16, bytes, flops);
+  ProfScope ps(c, 0, bytes, flops);
+  if (Lv.qcap < q) return fail(c, HH_EDEVICE, "leaf solve work space smaller than the launch needs");
+  if (c->precision == HH_MIXED) {
+    HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, Lv.W, par, out,
+                                      c->stream));
+  } else {
+    HH_CHECK(launch_leaf_solve<double>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G, rhs, x, Lv.W, par, out,
+                                       c->stream));
   }
   return HH_OK;
 }
@@ -316,18 +341,7 @@ hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
 // two-level steps from zero on the box problem.
 hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x) {
   Level& Lv = c->lv[l];
-  if (l == c->L) {
-    double bytes = 0.0, flops = 0.0;
-    if (c->prof) leaf_solve_cost(Lv, q, c->precision == HH_MIXED ? 8 : 16, bytes, flops);
-    ProfScope ps(c, 0, bytes, flops);
-    if (Lv.qcap < q) return fail(c, HH_EDEVICE, "leaf solve work space smaller than the launch needs");
-    if (c->precision == HH_MIXED) {
-      HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, Lv.W, c->stream));
-    } else {
-      HH_CHECK(launch_leaf_solve<double>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G, rhs, x, Lv.W, c->stream));
-    }
-    return HH_OK;
-  }
+  if (l == c->L) return leaf_solve(c, q, rhs, x, nullptr, nullptr);
   const int ni = std::max(1, c->inner[l]);
   HH_TRY(two_level(c, l, q, rhs, x));
   for (int it = 1; it < ni; ++it) {

@@ -209,10 +209,13 @@ __device__ __forceinline__ long long owned_to_parent(const BoxDev& B, const BoxD
 }
 
 constexpr int RCH = 256;  // owned nodes per restrict work-group (split of the inner dimension)
+constexpr int KU = 8;     // inner steps whose operands are loaded before their products
 
 // part[box][chunk][a][c] = sum over the chunk's owned nodes e of conj(C[e][a]) t[c][e]
 // (a < MT 16 padded, c < q padded to 64).  Wave w: right-hand sides 16 w .. 16 w + 15
-// of the work-group's 64; MT tiles of 16 coarse vectors.
+// of the work-group's 64; MT tiles of 16 coarse vectors.  Operands of KU
+// steps of four nodes are loaded before their products, so KU (1 + MT) loads
+// per lane are in flight.
 template <int MT>
 __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
                                                       int nchunk, int q, int qpad, const c128* __restrict__ C,
@@ -228,19 +231,27 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__
   const int e1 = e0 + RCH < B.n_own ? e0 + RCH : B.n_own;
   const c128* tb = t + P.voff * q + (long long)(c < q ? c : 0) * P.n;
   const c128* Cb = C + B.coff;
+  constexpr int U = MT <= 2 ? KU : MT <= 4 ? KU / 2 : KU / 4;  // loads in flight within the register budget
   d4 re[MT], im[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) re[mt] = im[mt] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = e0; k0 < e1; k0 += 4) {
-    const int e = k0 + kk;
-    const bool ve = e < e1;
-    const double2 tv = (ve && c < q) ? tb[owned_to_parent(B, P, e)] : mk(0.0, 0.0);
+  for (int k0 = e0; k0 < e1; k0 += 4 * U) {
+    double2 tv[U], cv[U][MT];
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int a = mt * 16 + m;
-      const double2 cv = (ve && a < B.r) ? Cb[(long long)a * B.n_own + e] : mk(0.0, 0.0);
-      cmfma_ca(cv, tv, re[mt], im[mt]);
+    for (int u = 0; u < U; ++u) {
+      const int e = k0 + 4 * u + kk;
+      const bool ve = e < e1;
+      tv[u] = (ve && c < q) ? tb[owned_to_parent(B, P, e)] : mk(0.0, 0.0);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int a = mt * 16 + m;
+        cv[u][mt] = (ve && a < B.r) ? Cb[(long long)a * B.n_own + e] : mk(0.0, 0.0);
+      }
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) cmfma_ca(cv[u][mt], tv[u], re[mt], im[mt]);
   }
   c128* pb = part + ((long long)box * nchunk + chunk) * (MT * 16) * qpad;
   const int cc = blockIdx.y * 64 + wave * 16 + (lane & 15);
@@ -270,68 +281,97 @@ __global__ void __launch_bounds__(TB) k_restrict_sum(const BoxDev* __restrict__ 
   cvec[D.yoff * q + (long long)c * D.n_c + B.cidx + a] = s;
 }
 
-// y[par][c] = A_c^{-1} cvec[par][c]: one wave per 16 x 16 output tile (rows of
-// A_c^{-1} x right-hand sides), inner dimension n_c in steps of four.
-__global__ void __launch_bounds__(TB) k_coarse_gemm(const ParentDev* __restrict__ pd, int q, int mtiles, int ntiles,
+// y[par][c] = A_c^{-1} cvec[par][c]: one work-group per 16 x 16 output tile
+// (rows of A_c^{-1} x right-hand sides); its four waves take interleaved
+// quarters of the inner dimension (KU steps of four at a time) and meet in LDS.
+__global__ void __launch_bounds__(TB) k_coarse_gemm(const ParentDev* __restrict__ pd, int q, int ntiles,
                                                     const c128* __restrict__ Ainv, const c128* __restrict__ cvec,
                                                     c128* __restrict__ y) {
-  const int pb = blockIdx.y;
-  const ParentDev D = pd[pb];
+  const ParentDev D = pd[blockIdx.y];
   const int n = D.n_c;
-  const int tile = blockIdx.x * (TB / 64) + (threadIdx.x >> 6);
-  if (tile >= mtiles * ntiles) return;
-  const int mt = tile / ntiles, nt = tile - mt * ntiles;
+  const int mt = blockIdx.x / ntiles, nt = blockIdx.x - mt * ntiles;
   if (mt * 16 >= n) return;
-  const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, m = lane & 15, kk = lane >> 4;
   const int row = mt * 16 + m, col = nt * 16 + m;
   const c128* A = Ainv + D.aoff;
   const c128* cv = cvec + D.yoff * q;
   d4 re = {0.0, 0.0, 0.0, 0.0}, im = re;
-  for (int k0 = 0; k0 < n; k0 += 4) {
-    const int k = k0 + kk;
-    const double2 av = (row < n && k < n) ? A[row + (long long)k * n] : mk(0.0, 0.0);
-    const double2 bv = (k < n && col < q) ? cv[(long long)col * n + k] : mk(0.0, 0.0);
-    cmfma(av, bv, re, im);
+  for (int k0 = wave * 4 * KU; k0 < n; k0 += 4 * 4 * KU) {
+    double2 av[KU], bv[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = k0 + 4 * u + kk;
+      av[u] = (row < n && k < n) ? A[row + (long long)k * n] : mk(0.0, 0.0);
+      bv[u] = (k < n && col < q) ? cv[(long long)col * n + k] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) cmfma(av[u], bv[u], re, im);
   }
-  const int cc = nt * 16 + (lane & 15);
-  if (cc < q) {
+  __shared__ double2 red[4][256];
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl) red[wave][sl * 64 + lane] = mk(re[sl], im[sl]);
+  __syncthreads();
+  if (wave == 0) {
+    const int cc = nt * 16 + (lane & 15);
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
+      const double2 v = cadd(cadd(red[0][sl * 64 + lane], red[1][sl * 64 + lane]),
+                             cadd(red[2][sl * 64 + lane], red[3][sl * 64 + lane]));
       const int r = mt * 16 + 4 * sl + (lane >> 4);
-      if (r < n) y[D.yoff * q + (long long)cc * n + r] = mk(re[sl], im[sl]);
+      if (r < n && cc < q) y[D.yoff * q + (long long)cc * n + r] = v;
     }
   }
 }
 
 // u[par][c][owned nodes of child] += C_child y: computed transposed,
 // (y^T C^T)[c][e], so that a wave's D tile spans 16 consecutive owned nodes.
-// Wave: 16 nodes x 64 right-hand sides (four tiles); inner dimension r.
+// Wave: 16 nodes x 64 right-hand sides (four tiles); inner dimension r.  The
+// work-group's y block (r x 64) is staged in LDS once; each lane loads its C
+// column slice (KU steps) before the products.
+constexpr int PR_MAXR = 128;
+
 __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
                                                      const ParentDev* __restrict__ pd, int ngroups, int q,
                                                      const c128* __restrict__ C, const c128* __restrict__ y,
                                                      c128* __restrict__ u) {
   const int box = blockIdx.x / ngroups;
   const BoxDev B = child[box];
-  const int e0 = ((blockIdx.x % ngroups) * (TB / 64) + (threadIdx.x >> 6)) * 16;
-  if (B.r == 0 || e0 >= B.n_own) return;
+  const int g0 = (blockIdx.x % ngroups) * (TB / 64) * 16;
+  if (B.r == 0 || g0 >= B.n_own) return;
   const BoxDev P = par[B.parent];
   const ParentDev D = pd[B.parent];
-  const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
   const int c0 = blockIdx.y * 64;
-  const c128* yb = y + D.yoff * q + B.cidx;
+  extern __shared__ double2 ys[];  // ys[c][a], 64 x (r + 1)
+  const int rs = B.r + 1;
+  for (int idx = threadIdx.x; idx < 64 * B.r; idx += TB) {
+    const int cl = idx / B.r, a = idx - cl * B.r;
+    const int c = c0 + cl;
+    ys[cl * rs + a] = c < q ? y[D.yoff * q + (long long)c * D.n_c + B.cidx + a] : mk(0.0, 0.0);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
+  const int e0 = g0 + (threadIdx.x >> 6) * 16;
+  if (e0 >= B.n_own) return;
   const c128* Cb = C + B.coff;
   const int en = e0 + m;
   d4 re[4], im[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) re[t] = im[t] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < B.r; k0 += 4) {
-    const int a = k0 + kk;
-    const double2 cv = (a < B.r && en < B.n_own) ? Cb[(long long)a * B.n_own + en] : mk(0.0, 0.0);
+  for (int k0 = 0; k0 < B.r; k0 += 4 * KU) {
+    double2 cv[KU];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int c = c0 + 16 * t + m;
-      const double2 yv = (a < B.r && c < q) ? yb[(long long)c * D.n_c + a] : mk(0.0, 0.0);
-      cmfma(yv, cv, re[t], im[t]);
+    for (int uu = 0; uu < KU; ++uu) {
+      const int a = k0 + 4 * uu + kk;
+      cv[uu] = (a < B.r && en < B.n_own) ? Cb[(long long)a * B.n_own + en] : mk(0.0, 0.0);
+    }
+#pragma unroll
+    for (int uu = 0; uu < KU; ++uu) {
+      const int a = k0 + 4 * uu + kk;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double2 yv = a < B.r ? ys[(16 * t + m) * rs + a] : mk(0.0, 0.0);
+        cmfma(yv, cv[uu], re[t], im[t]);
+      }
     }
   }
   const int e = e0 + (lane & 15);
@@ -426,18 +466,18 @@ hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, 
                               const c128* cvec, c128* y, hipStream_t s) {
   if (npar <= 0 || max_nc <= 0 || q <= 0) return hipSuccess;
   const int mtiles = (max_nc + 15) / 16, ntiles = (q + 15) / 16;
-  const int tiles = mtiles * ntiles;
-  hipLaunchKernelGGL(k_coarse_gemm, dim3((tiles + 3) / 4, npar), dim3(TB), 0, s, pd, q, mtiles, ntiles, Ainv, cvec,
-                     y);
+  hipLaunchKernelGGL(k_coarse_gemm, dim3(mtiles * ntiles, npar), dim3(TB), 0, s, pd, q, ntiles, Ainv, cvec, y);
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
+hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, int rmax, const BoxDev* par,
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
                                  hipStream_t s) {
   if (nchild <= 0 || q <= 0) return hipSuccess;
+  if (rmax > PR_MAXR) return hipErrorInvalidValue;
   const int ngroups = (max_own + 63) / 64;
-  hipLaunchKernelGGL(k_prolong_mfma, dim3(nchild * ngroups, (q + 63) / 64), dim3(TB), 0, s, child, par, pd, ngroups,
+  const size_t shm = sizeof(double2) * 64 * (size_t)(rmax + 1);
+  hipLaunchKernelGGL(k_prolong_mfma, dim3(nchild * ngroups, (q + 63) / 64), dim3(TB), shm, s, child, par, pd, ngroups,
                      q, C, y, u);
   return hipGetLastError();
 }

@@ -138,7 +138,7 @@ template <typename T, int QB, int TM, int R, int NW, bool PF>
 __global__ void __launch_bounds__(64 * NW)
     k_sweep(OpDev op, const BoxDev* __restrict__ leaves, int nunit, int nchunk, int q, int phase,
             const typename cvec<T>::type* __restrict__ G, const c128* __restrict__ rhs, c128* __restrict__ x,
-            c128* __restrict__ edge, int edge_ld) {
+            c128* __restrict__ edge, int edge_ld, const BoxDev* __restrict__ par, c128* __restrict__ out) {
   typedef typename cvec<T>::type CT;
   constexpr int NT = 64 * NW, RG = 8 * NW, M0 = TM * QB;
   constexpr int YS = R * QB + 1;  // LDS stride of a column slice (odd: slices start on different banks)
@@ -178,6 +178,16 @@ __global__ void __launch_bounds__(64 * NW)
   const int rgi = wave * 8 + ((lane >> 1) & 7);
   const int c0 = chunk * QB;
   const long long base = B.voff * q;
+  // right-hand side: the box's own vector, or (par given) read in place from
+  // the parent's vector; node (line, i) of column c at rbase + c rcol + line rrow + i
+  long long rbase = base, rcol = B.n;
+  int rrow = b;
+  if (par) {
+    const BoxDev P = par[B.parent];
+    rbase = P.voff * q + (long long)(B.p0 - P.p0) * P.ny + (B.q0 - P.q0);
+    rcol = P.n;
+    rrow = P.ny;
+  }
   const long long bb = (long long)b * b;
   const CT* Gl = G + B.goff;
   const CT zero = mk((T)0, (T)0);
@@ -196,12 +206,13 @@ __global__ void __launch_bounds__(64 * NW)
     own[t] = (t % SM::dups) == sdup && orow[t] < b && c0 + c < q;
   }
   // clamped addresses for branch-free prefetches (used only where own[t])
-  long long oaddr[MF];
+  long long oaddr[MF], raddr[MF];
 #pragma unroll
   for (int t = 0; t < MF; ++t) {
     const int i = orow[t] < b ? orow[t] : b - 1;
     const int c = c0 + ocol[t] < q ? c0 + ocol[t] : q - 1;
     oaddr[t] = base + (long long)c * B.n + i;
+    raddr[t] = rbase + (long long)c * rcol + i;
   }
 
   // G slice of the first line into registers (PF: the next line's slice is
@@ -224,8 +235,7 @@ __global__ void __launch_bounds__(64 * NW)
     const int i = e % b, c = e / b;
     double2 v = mk(0.0, 0.0);
     if (c0 + c < q) {
-      const long long col = base + (long long)(c0 + c) * B.n;
-      v = rhs[col + (long long)l0 * b + i];
+      v = rhs[rbase + (long long)(c0 + c) * rcol + (long long)l0 * rrow + i];
       if (phase == 2) {
         const int p = B.p0 + m, qq = B.q0 + i;
         if (n_top > 0) {
@@ -248,11 +258,12 @@ __global__ void __launch_bounds__(64 * NW)
     const int jn = more ? j + dl : j;
     // epilogue operands: phase 1 needs b_{j+dl}; phase 2 (s > 0) needs w_j / v_j
     double2 pre[MF];
-    {
-      const long long loff = (long long)(phase == 1 ? jn : j) * b;
-      const c128* src = phase == 1 ? rhs : x;
+    if (phase == 1) {
 #pragma unroll
-      for (int t = 0; t < MF; ++t) pre[t] = src[oaddr[t] + loff];
+      for (int t = 0; t < MF; ++t) pre[t] = rhs[raddr[t] + (long long)jn * rrow];
+    } else {
+#pragma unroll
+      for (int t = 0; t < MF; ++t) pre[t] = x[oaddr[t] + (long long)j * b];
     }
     // issued here, consumed in the epilogue: kept ahead of the next line's G
     // loads so that waiting for them leaves those in flight
@@ -303,7 +314,13 @@ __global__ void __launch_bounds__(64 * NW)
         x[at] = xv;
         if (!more) edge[((long long)unit * q + c0 + c) * edge_ld + i] = xv;
       } else if (s > 0 || half == 0) {
-        x[at] = xv;
+        if (!out) {
+          x[at] = xv;
+        } else {
+          // the restricted prolongation: owned nodes straight into the parent's vector
+          const int p = B.p0 + j, qq = B.q0 + i;
+          if (p >= B.op0 && p <= B.op1 && qq >= B.oq0 && qq <= B.oq1) out[raddr[t] + (long long)j * rrow] = xv;
+        }
       }
       if (more) {
         const double2 a = stencil_coef(op, B.p0, B.p1, B.q0, B.q1, B.p0 + jn, B.q0 + i, j - jn, 0);
@@ -317,12 +334,13 @@ __global__ void __launch_bounds__(64 * NW)
 
 template <typename T, int QB, int TM, int R, int NW, bool PF>
 hipError_t launch_sweep(const OpDev& op, const BoxDev* leaves, int nleaf, int q, const typename cvec<T>::type* G,
-                        const c128* rhs, c128* x, c128* edge, int edge_ld, hipStream_t s) {
+                        const c128* rhs, c128* x, c128* edge, int edge_ld, const BoxDev* par, c128* out,
+                        hipStream_t s) {
   const int nchunk = (q + QB - 1) / QB, nunit = 2 * nleaf;
   const dim3 grid(nunit * nchunk), block(64 * NW);
   for (int phase = 1; phase <= 2; ++phase) {
     hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF>), grid, block, 0, s, op, leaves, nunit, nchunk, q, phase, G, rhs,
-                       x, edge, edge_ld);
+                       x, edge, edge_ld, par, out);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -333,13 +351,13 @@ hipError_t launch_sweep(const OpDev& op, const BoxDev* leaves, int nleaf, int q,
 // up to four columns per group to amortise the G_j stream.
 template <typename T, int TM, int R, int NW, bool PF>
 hipError_t launch_qb(const OpDev& op, const BoxDev* leaves, int nleaf, int q, const typename cvec<T>::type* G,
-                     const c128* rhs, c128* x, c128* edge, int edge_ld, hipStream_t s) {
+                     const c128* rhs, c128* x, c128* edge, int edge_ld, const BoxDev* par, c128* out, hipStream_t s) {
   const long long units = 2LL * nleaf;
   if (q >= 4 && units * ((q + 3) / 4) >= 256)
-    return launch_sweep<T, 4, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, s);
+    return launch_sweep<T, 4, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, par, out, s);
   if (q >= 2 && units * ((q + 1) / 2) >= 128)
-    return launch_sweep<T, 2, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, s);
-  return launch_sweep<T, 1, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, s);
+    return launch_sweep<T, 2, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, par, out, s);
+  return launch_sweep<T, 1, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, par, out, s);
 }
 
 }  // namespace
@@ -349,24 +367,25 @@ hipError_t launch_qb(const OpDev& op, const BoxDev* leaves, int nleaf, int q, co
 // covered by 8 NW row groups of TM rows.
 template <typename T>
 hipError_t launch_leaf_solve(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, int q,
-                             const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge, hipStream_t s) {
+                             const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge,
+                             const BoxDev* par, c128* out, hipStream_t s) {
   if (nleaf <= 0 || q <= 0) return hipSuccess;
-  if (max_ny <= 8) return launch_qb<T, 1, 1, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, s);
-  if (max_ny <= 16) return launch_qb<T, 2, 2, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, s);
-  if (max_ny <= 40) return launch_qb<T, 5, 5, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, s);
-  if (max_ny <= 72) return launch_qb<T, 3, 9, 3, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, s);
+  if (max_ny <= 8) return launch_qb<T, 1, 1, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
+  if (max_ny <= 16) return launch_qb<T, 2, 2, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
+  if (max_ny <= 40) return launch_qb<T, 5, 5, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
+  if (max_ny <= 72) return launch_qb<T, 3, 9, 3, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
   // wider boxes: the 3 x 18 G slice stays in registers in complex64 only; the
   // 256-wide bucket loads G at use
   if constexpr (sizeof(T) == 4) {
-    if (max_ny <= 144) return launch_qb<T, 3, 18, 6, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, s);
+    if (max_ny <= 144) return launch_qb<T, 3, 18, 6, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
   } else {
-    if (max_ny <= 144) return launch_qb<T, 3, 18, 6, false>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, s);
+    if (max_ny <= 144) return launch_qb<T, 3, 18, 6, false>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
   }
-  if (max_ny <= 256) return launch_qb<T, 4, 32, 8, false>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, s);
+  if (max_ny <= 256) return launch_qb<T, 4, 32, 8, false>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_leaf_solve<double>(const OpDev&, const BoxDev*, int, int, int, const c128*, const c128*,
-                                              c128*, c128*, hipStream_t);
+                                              c128*, c128*, const BoxDev*, c128*, hipStream_t);
 template hipError_t launch_leaf_solve<float>(const OpDev&, const BoxDev*, int, int, int, const c64*, const c128*,
-                                             c128*, c128*, hipStream_t);
+                                             c128*, c128*, const BoxDev*, c128*, hipStream_t);

@@ -8,33 +8,39 @@ namespace {
 
 constexpr int TB = 256;
 
-// One 5-point row of the cell-assembled box matrix applied to a local vector.
-__device__ __forceinline__ double2 apply_row(const OpDev& op, const BoxDev& B, const c128* __restrict__ x,
-                                             int a, int c) {
-  const int p = B.p0 + a, q = B.q0 + c;
-  const int l = a * B.ny + c;
-  double2 acc = cmul(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 0, 0), x[l]);
-  if (a > 0) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, -1, 0), x[l - B.ny], acc);
-  if (a < B.nx - 1) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 1, 0), x[l + B.ny], acc);
-  if (op.dim == 2) {
-    if (c > 0) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 0, -1), x[l - 1], acc);
-    if (c < B.ny - 1) acc = cfma(stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 0, 1), x[l + 1], acc);
-  }
-  return acc;
-}
+// y = A_box x (mode 0) or y = b - A_box x (mode 1): one thread per node of a
+// box, its five stencil coefficients formed once and applied to QG columns.
+constexpr int QG = 16;
 
 __global__ void __launch_bounds__(TB) k_apply_box(OpDev op, const BoxDev* __restrict__ boxes, int q,
                                                   const c128* __restrict__ x, const c128* __restrict__ b,
                                                   c128* __restrict__ y, int mode) {
-  const int bc = blockIdx.y;
-  const int box = bc / q, col = bc % q;
-  const BoxDev B = boxes[box];
-  const long long base = B.voff * q + (long long)col * B.n;
-  for (int l = blockIdx.x * TB + threadIdx.x; l < B.n; l += gridDim.x * TB) {
-    const int a = l / B.ny, c = l - a * B.ny;
-    double2 v = apply_row(op, B, x + base, a, c);
-    if (mode == 1) v = csub(b[base + l], v);
-    y[base + l] = v;
+  const BoxDev B = boxes[blockIdx.y];
+  const int l = blockIdx.x * TB + threadIdx.x;
+  if (l >= B.n) return;
+  const int a = l / B.ny, c = l - a * B.ny;
+  const int p = B.p0 + a, qq = B.q0 + c;
+  const double2 z = mk(0.0, 0.0);
+  const double2 cd = stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, qq, 0, 0);
+  const bool hw = a > 0, he = a < B.nx - 1, hs = op.dim == 2 && c > 0, hn = op.dim == 2 && c < B.ny - 1;
+  const double2 cw = hw ? stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, qq, -1, 0) : z;
+  const double2 ce = he ? stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, qq, 1, 0) : z;
+  const double2 cs = hs ? stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, qq, 0, -1) : z;
+  const double2 cn = hn ? stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, qq, 0, 1) : z;
+  // absent neighbours read the node itself with a zero coefficient
+  const int lw = hw ? l - B.ny : l, le = he ? l + B.ny : l, ls = hs ? l - 1 : l, ln = hn ? l + 1 : l;
+  const int c0 = blockIdx.z * QG, c1 = c0 + QG < q ? c0 + QG : q;
+#pragma unroll 4
+  for (int col = c0; col < c1; ++col) {
+    const c128* xb = x + B.voff * q + (long long)col * B.n;
+    double2 v = cmul(cd, xb[l]);
+    v = cfma(cw, xb[lw], v);
+    v = cfma(ce, xb[le], v);
+    v = cfma(cs, xb[ls], v);
+    v = cfma(cn, xb[ln], v);
+    const long long at = B.voff * q + (long long)col * B.n + l;
+    if (mode == 1) v = csub(b[at], v);
+    y[at] = v;
   }
 }
 
@@ -131,7 +137,7 @@ inline int grid_for(long long n, int cap = 4096) {
 hipError_t launch_apply_box(const OpDev& op, const BoxDev* boxes, int nbox, int max_n, int q,
                             const c128* x, const c128* b, c128* y, int mode, hipStream_t s) {
   if (nbox <= 0 || q <= 0) return hipSuccess;
-  dim3 grid(grid_for(max_n, 1024), nbox * q);
+  dim3 grid((max_n + TB - 1) / TB, nbox, (q + QG - 1) / QG);
   hipLaunchKernelGGL(k_apply_box, grid, dim3(TB), 0, s, op, boxes, q, x, b, y, mode);
   return hipGetLastError();
 }

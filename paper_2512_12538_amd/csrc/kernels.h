@@ -36,10 +36,14 @@ hipError_t launch_leaf_factor(const OpDev& op, const BoxDev* leaves, int nleaf, 
 // x = A~^{-1} rhs for every leaf box and q columns (two launches).  rhs and x
 // are distinct level buffers; edge holds 2 nleaf * q * max_ny entries of work
 // space.  G (T = double: FP64 factors, float: complex64 copy) needs 65536
-// readable entries past its end.
+// readable entries past its end.  With par (the parent level's boxes) rhs is
+// the parent level's buffer, read in place (R_i rhs), and with out the solution
+// goes to the parent buffer on the owned nodes only (P_i x, every parent node
+// owned by one leaf); x then serves as work space.
 template <typename T>
 hipError_t launch_leaf_solve(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, int q,
-                             const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge, hipStream_t s);
+                             const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge,
+                             const BoxDev* par, c128* out, hipStream_t s);
 
 // ---------------------------------------------------------------- interface map / rSVD (k_rsvd.hip)
 // buf[box][c][iface[t]] = vals[voff[box] + c*m_in + t] for c < (use_r ? r : s); buf pre-zeroed
@@ -89,7 +93,7 @@ hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, int max_own, 
 hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, const c128* Ainv,
                               const c128* cvec, c128* y, hipStream_t s);
 // u[par][c][owned nodes of child] += C_child y[par][c][cidx ..] (FP64 matrix cores)
-hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
+hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, int rmax, const BoxDev* par,
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
                                  hipStream_t s);
 
