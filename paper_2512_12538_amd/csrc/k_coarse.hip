@@ -208,7 +208,7 @@ __device__ __forceinline__ long long owned_to_parent(const BoxDev& B, const BoxD
   return (long long)(B.op0 + oa - P.p0) * P.ny + (B.oq0 + oc - P.q0);
 }
 
-constexpr int RCH = 256;  // owned nodes per restrict work-group (split of the inner dimension)
+constexpr int RCH = 128;  // owned nodes per restrict work-group (split of the inner dimension)
 constexpr int KU = 8;     // inner steps whose operands are loaded before their products
 
 // part[box][chunk][a][c] = sum over the chunk's owned nodes e of conj(C[e][a]) t[c][e]
@@ -251,7 +251,8 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) cmfma_ca(cv[u][mt], tv[u], re[mt], im[mt]);
+      for (int mt = 0; mt < MT; ++mt)
+        if (mt * 16 < B.r) cmfma_ca(cv[u][mt], tv[u], re[mt], im[mt]);  // tiles past this box's rank skipped
   }
   c128* pb = part + ((long long)box * nchunk + chunk) * (MT * 16) * qpad;
   const int cc = blockIdx.y * 64 + wave * 16 + (lane & 15);
@@ -366,6 +367,7 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ 
     }
 #pragma unroll
     for (int uu = 0; uu < KU; ++uu) {
+      if (k0 + 4 * uu >= B.r) break;  // steps past this box's rank skipped
       const int a = k0 + 4 * uu + kk;
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
@@ -376,16 +378,13 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ 
   }
   const int e = e0 + (lane & 15);
   if (e < B.n_own) {
-    const long long pl = owned_to_parent(B, P, e);
+    c128* ub = u + P.voff * q + owned_to_parent(B, P, e);
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         const int c = c0 + 16 * t + 4 * sl + (lane >> 4);
-        if (c < q) {
-          c128* uv = u + P.voff * q + (long long)c * P.n + pl;
-          *uv = cadd(*uv, mk(re[t][sl], im[t][sl]));
-        }
+        if (c < q) ub[(long long)c * P.n] = cadd(ub[(long long)c * P.n], mk(re[t][sl], im[t][sl]));
       }
   }
 }

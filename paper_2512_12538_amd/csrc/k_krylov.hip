@@ -275,12 +275,19 @@ __global__ void __launch_bounds__(TB) k_normalize(int q, long long n, const c128
 // previous rotations, a new rotation zeroing H[j+1, j], the update of g, and
 // the stopping test |g_{j+1}| < thr[b] or iters[b] >= maxit.
 // Layout per rhs b: H[b][(m+1)*col + row], cs/sn[b][m], g[b][m+1].
-__global__ void k_gmres_step(int q, int j, int m, c128* __restrict__ H, const c128* __restrict__ h1,
-                             const c128* __restrict__ h2, const double* __restrict__ hnext,
-                             c128* __restrict__ cs, c128* __restrict__ sn, c128* __restrict__ g,
-                             double* __restrict__ est, int* __restrict__ st, const double* __restrict__ thr,
-                             int maxit) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per right-hand side: the lanes stage the column and the rotations
+// in LDS, lane 0 applies the rotations in order, the lanes write back.
+constexpr int GW = 4;  // right-hand sides (waves) per work-group
+
+__global__ void __launch_bounds__(64 * GW) k_gmres_step(int q, int j, int m, c128* __restrict__ H,
+                                                        const c128* __restrict__ h1, const c128* __restrict__ h2,
+                                                        const double* __restrict__ hnext, c128* __restrict__ cs,
+                                                        c128* __restrict__ sn, c128* __restrict__ g,
+                                                        double* __restrict__ est, int* __restrict__ st,
+                                                        const double* __restrict__ thr, int maxit) {
+  __shared__ double2 col_s[GW][128], cs_s[GW][128], sn_s[GW][128];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int b = blockIdx.x * GW + wv;
   if (b >= q) return;
   int* active = st;
   int* jdone = st + q;
@@ -291,35 +298,51 @@ __global__ void k_gmres_step(int q, int j, int m, c128* __restrict__ H, const c1
   c128* sb = sn + (long long)b * m;
   c128* gb = g + (long long)b * (m + 1);
   c128* col = Hb + (long long)(m + 1) * j;
-  for (int t = 0; t <= j; ++t) col[t] = cadd(h1[t * q + b], h2[t * q + b]);
-  col[j + 1] = mk(hnext[b], 0.0);
-  for (int t = 0; t < j; ++t) {
-    const double2 a = col[t], bb = col[t + 1];
-    col[t] = cadd(cmulc(cb[t], a), cmulc(sb[t], bb));
-    col[t + 1] = csub(cmul(cb[t], bb), cmul(sb[t], a));
+  double2* cl = col_s[wv];
+  for (int t = lane; t <= j + 1; t += 64) {
+    cl[t] = t <= j ? cadd(h1[t * q + b], h2[t * q + b]) : mk(hnext[b], 0.0);
+    if (t < j) {
+      cs_s[wv][t] = cb[t];
+      sn_s[wv][t] = sb[t];
+    }
   }
-  const double2 a = col[j], bb = col[j + 1];
-  const double den = sqrt(cabs2(a) + cabs2(bb));
-  double2 c, s;
-  if (den == 0.0) {
-    c = mk(1.0, 0.0);
-    s = mk(0.0, 0.0);
-  } else {
-    c = cscale(a, 1.0 / den);
-    s = cscale(bb, 1.0 / den);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  if (lane == 0) {
+    for (int t = 0; t < j; ++t) {
+      const double2 a = cl[t], bb = cl[t + 1], c = cs_s[wv][t], s = sn_s[wv][t];
+      cl[t] = cadd(cmulc(c, a), cmulc(s, bb));
+      cl[t + 1] = csub(cmul(c, bb), cmul(s, a));
+    }
+    const double2 a = cl[j], bb = cl[j + 1];
+    const double den = sqrt(cabs2(a) + cabs2(bb));
+    double2 c, s;
+    if (den == 0.0) {
+      c = mk(1.0, 0.0);
+      s = mk(0.0, 0.0);
+    } else {
+      c = cscale(a, 1.0 / den);
+      s = cscale(bb, 1.0 / den);
+    }
+    cb[j] = c;
+    sb[j] = s;
+    cl[j] = mk(den, 0.0);
+    cl[j + 1] = mk(0.0, 0.0);
+    const double2 gj = gb[j];
+    gb[j + 1] = mk(-(s.x * gj.x - s.y * gj.y), -(s.x * gj.y + s.y * gj.x));
+    gb[j] = cmulc(c, gj);
+    const double e = sqrt(cabs2(gb[j + 1]));
+    est[b] = e;
+    jdone[b] = j + 1;
+    const int it = iters[b] + 1;
+    iters[b] = it;
+    if (e < thr[b] || it >= maxit) active[b] = 0;
   }
-  cb[j] = c;
-  sb[j] = s;
-  col[j] = mk(den, 0.0);
-  col[j + 1] = mk(0.0, 0.0);
-  const double2 gj = gb[j];
-  gb[j + 1] = mk(-(s.x * gj.x - s.y * gj.y), -(s.x * gj.y + s.y * gj.x));
-  gb[j] = cmulc(c, gj);
-  const double e = sqrt(cabs2(gb[j + 1]));
-  est[b] = e;
-  jdone[b] = j + 1;
-  iters[b] += 1;
-  if (e < thr[b] || iters[b] >= maxit) active[b] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (int t = lane; t <= j + 1; t += 64) col[t] = cl[t];
 }
 
 // any[0] = number of active right-hand sides
@@ -412,8 +435,9 @@ hipError_t launch_gmres_step(int q, int j, int m, c128* H, const c128* h1, const
                              c128* cs, c128* sn, c128* g, double* est, int* state, const double* thr, int maxit,
                              int* any, hipStream_t s) {
   if (q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gmres_step, dim3((q + 63) / 64), dim3(64), 0, s, q, j, m, H, h1, h2, hnext, cs, sn, g, est,
-                     state, thr, maxit);
+  if (m > 126) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gmres_step, dim3((q + GW - 1) / GW), dim3(64 * GW), 0, s, q, j, m, H, h1, h2, hnext, cs, sn, g,
+                     est, state, thr, maxit);
   hipLaunchKernelGGL(k_count_active, dim3(1), dim3(256), 0, s, q, state, any);
   return hipGetLastError();
 }
