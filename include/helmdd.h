@@ -168,6 +168,79 @@ hh_status hh_profile_read(hh_ctx* c, int32_t family, int64_t* launches, double* 
 
 hh_status hh_destroy(hh_ctx* c);
 
+/* ------------------------------------------------------------------ serving
+ * A server solves requests for many operators on one GPU: worker threads,
+ * each with its own HIP stream, take the oldest queued request whose operator
+ * is idle together with the other queued requests for that operator and
+ * tolerance (up to max_batch_rhs right-hand sides) and run them as one
+ * hh_solve.  Prepared operators (leaf factors and the coarse spaces of all
+ * levels, built with Gaussian blocks drawn by hh_omega_philox from the
+ * request's seed) stay on the device, keyed by operator_id.  A new operator
+ * is admitted when its estimated footprint plus the batch's work space fits
+ * budget_bytes, after idle operators are evicted least-recently-used first;
+ * otherwise it waits for running batches to end (HH_ENOMEM if it cannot fit
+ * even alone).  Every right-hand side gives the same result in any batch.
+ * Thread-safe: any thread may submit and wait. */
+typedef struct hh_server hh_server;
+
+typedef struct {
+  int64_t budget_bytes;  /* device bytes for prepared operators and running batches */
+  int32_t workers;       /* batches in flight, 1..16 (one stream each) */
+  int32_t max_batch_rhs; /* right-hand sides per batch (and per request), >= 1 */
+  int32_t precision;     /* hh_precision of every operator */
+  int32_t gmres_restart; /* 0: 50 */
+} hh_server_options;
+
+typedef struct {
+  uint64_t operator_id;           /* one id, one (operator, decomposition, ranks, seed) */
+  hh_operator op;                 /* k (host) copied at the first request of an id */
+  hh_decomposition decomposition;
+  int32_t rank_per_interface[8];  /* per level l at index l-1; 0: no coarse space there */
+  int32_t oversample;
+  uint64_t omega_seed;
+  int32_t nrhs;
+  const void* f;                  /* device c128 [nrhs][(N+1)^dim], valid until completion */
+  void* u;                        /* device c128 [nrhs][(N+1)^dim], written at completion */
+  double rtol;                    /* as hh_solve; batched only with equal rtol and maxit */
+  int32_t maxit;
+} hh_request;
+
+typedef struct {
+  int32_t status;       /* hh_status of the request (HH_ENOTCONV: some rhs missed rtol) */
+  int32_t iters;        /* largest preconditioner-application count over its rhs */
+  double rel_residual;  /* largest true relative residual over its rhs */
+  double latency_s;     /* submit to result in u (its stream synchronised) */
+  double queue_s;       /* submit to the start of its batch */
+  int32_t batch_rhs;    /* right-hand sides of the batch that carried it */
+  int32_t cache_hit;    /* 1 if its operator was already prepared */
+} hh_request_result;
+
+hh_status hh_server_create(const hh_server_options* o, hh_server** out);
+/* Queues a request; *ticket identifies it.  HH_EINVAL for an invalid request
+ * or an id reused with another shape. */
+hh_status hh_server_submit(hh_server* s, const hh_request* r, uint64_t* ticket);
+/* Waits (timeout_s < 0: without limit) for the request; HH_ESTATE on timeout.
+ * A completed ticket is released by the call that returns its result. */
+hh_status hh_server_wait(hh_server* s, uint64_t ticket, double timeout_s, hh_request_result* res);
+hh_status hh_server_stats(hh_server* s, int64_t* served, int64_t* misses, int64_t* evictions, int64_t* cached,
+                          int64_t* reserved_bytes);
+/* Stops the workers after their running batches; queued requests are dropped. */
+hh_status hh_server_destroy(hh_server* s);
+
+/* Host-side estimate of the device bytes of a prepared operator plus the work
+ * space of a solve with nrhs right-hand sides (what the server reserves when
+ * it admits a new operator).  rank: per level, as in hh_request. */
+hh_status hh_estimate_device_bytes(const hh_operator* A, const hh_decomposition* d, const int32_t* rank,
+                                   int32_t oversample, int32_t nrhs, int32_t gmres_restart, int32_t precision,
+                                   int64_t* bytes);
+
+/* The Gaussian test block Omega of (level, box) the server draws from a seed:
+ * s x m_in complex entries CN(0,1), row-major (sample t, node j), as
+ * interleaved (re, im) doubles into out (host).  Philox4x32-10 with counter
+ * (t * m_in + j, box, level, 0x4f4d4547) and key (seed low, high words); two
+ * 53-bit uniforms per entry, Box-Muller. */
+hh_status hh_omega_philox(uint64_t seed, int32_t level, int32_t box, int32_t m_in, int32_t s, double* out);
+
 /* Frees the device blocks cached by the library on the current device (blocks
  * released by destroyed contexts and by buffer regrowth); *bytes (if non-null)
  * receives the amount freed.  The cache holds at most a quarter of the device

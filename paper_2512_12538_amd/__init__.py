@@ -51,6 +51,24 @@ class hh_solve_info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("rel_residual", ctypes.c_double)]
 
 
+class hh_server_options(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_int64), ("workers", ctypes.c_int32), ("max_batch_rhs", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("gmres_restart", ctypes.c_int32)]
+
+
+class hh_request(ctypes.Structure):
+    _fields_ = [("operator_id", ctypes.c_uint64), ("op", hh_operator), ("decomposition", hh_decomposition),
+                ("rank_per_interface", ctypes.c_int32 * 8), ("oversample", ctypes.c_int32),
+                ("omega_seed", ctypes.c_uint64), ("nrhs", ctypes.c_int32), ("f", ctypes.c_void_p),
+                ("u", ctypes.c_void_p), ("rtol", ctypes.c_double), ("maxit", ctypes.c_int32)]
+
+
+class hh_request_result(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double), ("batch_rhs", ctypes.c_int32),
+                ("cache_hit", ctypes.c_int32)]
+
+
 class HelmddError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"{_status_name(status)}: {message}")
@@ -86,6 +104,14 @@ def _load():
         "hh_profile": [P, i32],
         "hh_profile_read": [P, i32, P, P, P, P],
         "hh_release_cached_memory": [P],
+        "hh_server_create": [ctypes.POINTER(hh_server_options), ctypes.POINTER(P)],
+        "hh_server_submit": [P, ctypes.POINTER(hh_request), ctypes.POINTER(ctypes.c_uint64)],
+        "hh_server_wait": [P, ctypes.c_uint64, ctypes.c_double, ctypes.POINTER(hh_request_result)],
+        "hh_server_stats": [P, P, P, P, P, P],
+        "hh_server_destroy": [P],
+        "hh_omega_philox": [ctypes.c_uint64, i32, i32, i32, i32, P],
+        "hh_estimate_device_bytes": [ctypes.POINTER(hh_operator), ctypes.POINTER(hh_decomposition), P, i32, i32,
+                                     i32, i32, P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -289,3 +315,98 @@ def hh_destroy(ctx) -> None:
     if ctx is not None and ctx.handle:
         _check(_lib.hh_destroy(ctx))
         ctx.handle = ctypes.c_void_p()
+
+
+# ---------------------------------------------------------------- serving
+def hh_omega_philox(seed: int, level: int, box: int, m_in: int, s: int) -> np.ndarray:
+    """The Gaussian block the server draws for (level, box): shape (s, m_in), complex128."""
+    out = np.empty((s, m_in), dtype=np.complex128)
+    _check(_lib.hh_omega_philox(ctypes.c_uint64(seed), level, box, m_in, s, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def hh_estimate_device_bytes(dim: int, n_cells: int, decomp: hh_decomposition, ranks, oversample: int, nrhs: int,
+                             gmres_restart: int = 50, precision: int = HH_FP64) -> int:
+    """Device bytes the server reserves for a new operator and a solve of nrhs right-hand sides."""
+    op = hh_operator()
+    op.dim = dim
+    op.n_cells = n_cells
+    r = (ctypes.c_int32 * 8)(*([int(x) for x in ranks] + [0] * (8 - len(ranks))))
+    b = ctypes.c_int64(0)
+    _check(_lib.hh_estimate_device_bytes(ctypes.byref(op), ctypes.byref(decomp), r, oversample, nrhs, gmres_restart,
+                                         precision, ctypes.byref(b)))
+    return int(b.value)
+
+
+class Server:
+    """Serving loop of the C ABI (hh_server_*): continuous batching per operator id."""
+
+    def __init__(self, budget_bytes: int, workers: int = 2, max_batch_rhs: int = 64, precision: int = HH_FP64,
+                 gmres_restart: int = 50):
+        o = hh_server_options()
+        o.budget_bytes = int(budget_bytes)
+        o.workers = int(workers)
+        o.max_batch_rhs = int(max_batch_rhs)
+        o.precision = int(precision)
+        o.gmres_restart = int(gmres_restart)
+        self.handle = ctypes.c_void_p()
+        _check(_lib.hh_server_create(ctypes.byref(o), ctypes.byref(self.handle)))
+        self._keep = {}
+
+    def submit(self, operator_id: int, dim: int, n_cells: int, k, decomp: hh_decomposition, ranks, oversample: int,
+               omega_seed: int, f, u, rtol: float = 1e-8, maxit: int = 500) -> int:
+        """Queues a solve of f (device c128 [nrhs][n]) into u; returns the ticket."""
+        r = hh_request()
+        r.operator_id = int(operator_id)
+        r.op.dim = dim
+        r.op.n_cells = n_cells
+        keep = None
+        if np.isscalar(k):
+            r.op.k = None
+            r.op.k_const = float(k)
+        else:
+            keep = np.ascontiguousarray(k, dtype=np.float64)
+            r.op.k = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        r.decomposition = decomp
+        for l, rk in enumerate(ranks):
+            r.rank_per_interface[l] = int(rk)
+        r.oversample = int(oversample)
+        r.omega_seed = int(omega_seed)
+        n = (n_cells + 1) ** dim
+        if f.shape != u.shape or f.numel() % n or f.numel() == 0:
+            raise ValueError("f and u must have shape [nrhs, (N+1)^dim]")
+        r.nrhs = f.numel() // n
+        r.f = _dev(f)
+        r.u = _dev(u)
+        r.rtol = float(rtol)
+        r.maxit = int(maxit)
+        t = ctypes.c_uint64(0)
+        _check(_lib.hh_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = (f, u)  # tensors stay alive until the result is taken
+        del keep
+        return t.value
+
+    def wait(self, ticket: int, timeout_s: float = -1.0) -> dict:
+        res = hh_request_result()
+        _check(_lib.hh_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(res)))
+        self._keep.pop(ticket, None)
+        return dict(status=int(res.status), iters=int(res.iters), rel_residual=float(res.rel_residual),
+                    latency_s=float(res.latency_s), queue_s=float(res.queue_s), batch_rhs=int(res.batch_rhs),
+                    cache_hit=bool(res.cache_hit))
+
+    def stats(self) -> dict:
+        v = [ctypes.c_int64(0) for _ in range(5)]
+        _check(_lib.hh_server_stats(self.handle, *[ctypes.byref(x) for x in v]))
+        return dict(zip(["served", "misses", "evictions", "cached", "reserved_bytes"], [int(x.value) for x in v]))
+
+    def close(self) -> None:
+        if self.handle:
+            _check(_lib.hh_server_destroy(self.handle))
+            self.handle = ctypes.c_void_p()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

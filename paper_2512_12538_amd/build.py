@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libhelmdd.so")
 OBJDIR = os.path.join(ROOT, "_build", "obj")
 
-SOURCES = ["k_vec.hip", "k_leaf.hip", "k_sweep.hip", "k_rsvd.hip", "k_coarse.hip", "k_krylov.hip", "geometry.cpp", "pool.cpp", "api.cpp"]
+SOURCES = ["k_vec.hip", "k_leaf.hip", "k_sweep.hip", "k_rsvd.hip", "k_coarse.hip", "k_krylov.hip", "geometry.cpp", "pool.cpp", "rng.cpp", "server.cpp", "api.cpp"]
 ARCH = os.environ.get("HELMDD_ARCH", "gfx950")
 
 

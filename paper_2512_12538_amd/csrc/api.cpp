@@ -16,6 +16,7 @@
 
 #include "../../include/helmdd.h"
 #include "geometry.h"
+#include "internal.h"
 #include "kernels.h"
 #include "pool.h"
 
@@ -1153,3 +1154,55 @@ extern "C" hh_status hh_get_basis(hh_ctx* c, int32_t level, int32_t box, int32_t
   }
   return HH_OK;
 }
+
+// ------------------------------------------------------------------ serving hooks
+namespace helmdd_internal {
+
+hh_status set_stream(hh_ctx* c, hipStream_t s) {
+  if (!c) return HH_EINVAL;
+  if (c->stream == s) return HH_OK;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return HH_EDEVICE;
+  c->stream = s;
+  return HH_OK;
+}
+
+size_t resident_bytes(const hh_ctx* c) {
+  size_t n = 0;
+  if (c)
+    for (const DevBuf& b : c->allocs) n += b.bytes;
+  return n;
+}
+
+size_t estimate_bytes(const hh_operator* A, const hh_decomposition* d, const int32_t* rank, int32_t oversample,
+                      int32_t q, int32_t restart, int32_t precision) {
+  if (!A || !d || d->levels < 1 || d->levels > 8) return 0;
+  Geometry g;
+  if (!build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, g).empty()) return 0;
+  const double c16 = 16.0;
+  double bytes = 0.0;
+  // leaf factors: FP64 during the set-up (plus the complex64 copy when mixed)
+  double gl = 0.0;
+  for (const HBox& b : g.levels[g.depth()]) gl += (double)b.nx() * b.ny() * b.ny();
+  bytes += gl * c16 + (precision == HH_MIXED ? gl * 8.0 : 0.0);
+  const double n0 = (double)g.levels[0][0].n();
+  for (int l = 0; l <= g.depth(); ++l) {
+    double tot = 0.0, csz = 0.0, nc = 0.0;
+    for (const HBox& b : g.levels[l]) {
+      tot += b.n();
+      if (l >= 1) {
+        const double r = std::min<double>((double)rank[l - 1] * b.n_if, (double)b.iface.size());
+        const double s = std::min<double>(r + oversample, (double)b.iface.size());
+        csz += r * b.n_own() + s * b.iface.size() * 3.0;  // C, Omega / sketch blocks
+        nc += r;
+      }
+    }
+    const double qq = std::max(q, 1);
+    bytes += tot * qq * c16 * 6.0;      // level work buffers (R, X, T, E, U, W)
+    bytes += csz * c16 * 2.0;           // coarse blocks and Galerkin products
+    bytes += nc * nc * c16 * 2.0 + nc * qq * c16 * 2.0;
+  }
+  bytes += (2.0 * restart + 3.0) * n0 * std::max(q, 1) * c16;  // Krylov bases V, Z and work
+  return (size_t)bytes;
+}
+
+}  // namespace helmdd_internal

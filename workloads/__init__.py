@@ -122,3 +122,48 @@ WORKLOADS = {
                                   m=[(2, 2), (2, 2), (2, 2)], overlap=[8, 8, 8],
                                   rank=16, oversample=10, rhs="smooth"),
 }
+
+
+# ---------------------------------------------------------------- counter-based Gaussian blocks
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 (Salmon et al., SC 2011) on arrays of counters.
+
+    ctr: uint32 array (..., 4); key: two uint32 words.  Returns uint32 (..., 4).
+    """
+    c = [np.asarray(ctr[..., i], dtype=np.uint64) for i in range(4)]
+    k0, k1 = np.uint64(key[0]), np.uint64(key[1])
+    mask = np.uint64(0xFFFFFFFF)
+    for _ in range(10):
+        p0 = np.uint64(_PHILOX_M[0]) * c[0]
+        p1 = np.uint64(_PHILOX_M[1]) * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ k0, p1 & mask, (p0 >> np.uint64(32)) ^ c[3] ^ k1, p0 & mask]
+        k0 = (k0 + np.uint64(_PHILOX_W[0])) & mask
+        k1 = (k1 + np.uint64(_PHILOX_W[1])) & mask
+    return np.stack([x.astype(np.uint32) for x in c], axis=-1)
+
+
+def omega_philox(seed: int, level: int, box: int, m_in: int, s: int) -> np.ndarray:
+    """Gaussian test block drawn from a seed with Philox4x32-10: shape (s, m_in), CN(0,1).
+
+    Entry v = t*m_in + j uses counter (v, box, level, 0x4f4d4547) and key
+    (seed low, seed high); two 53-bit uniforms in (0, 1) per entry and the
+    Box-Muller transform give the real and imaginary parts (each / sqrt(2)).
+    """
+    n = m_in * s
+    v = np.arange(n, dtype=np.uint64)
+    ctr = np.stack([v & np.uint64(0xFFFFFFFF), np.full(n, box, np.uint64), np.full(n, level, np.uint64),
+                    np.full(n, 0x4F4D4547, np.uint64)], axis=-1).astype(np.uint32)
+    w = philox4x32_10(ctr, (seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)).astype(np.uint64)
+
+    def unit(hi, lo):
+        return (((hi << np.uint64(32)) | lo) >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0) + \
+            0.5 / 9007199254740992.0
+
+    u1, u2 = unit(w[:, 0], w[:, 1]), unit(w[:, 2], w[:, 3])
+    r = np.sqrt(-2.0 * np.log(u1)) / np.sqrt(2.0)
+    out = r * np.cos(2.0 * np.pi * u2) + 1j * (r * np.sin(2.0 * np.pi * u2))
+    return out.reshape(s, m_in)
