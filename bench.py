@@ -51,6 +51,11 @@ def parse():
     ap.add_argument("--cpu-rhs", type=int, default=2, help="right-hand sides in the CPU oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--serving-seconds", type=float, default=5.0,
+                    help="length of the request stream of the serving measurement (0: skip)")
+    ap.add_argument("--serving-rate", type=float, default=200.0, help="mean request arrivals per second")
+    ap.add_argument("--serving-drain", type=float, default=25.0,
+                    help="seconds to wait for queued requests after the stream ends")
     return ap.parse_args()
 
 
@@ -204,6 +209,116 @@ def cpu_baseline(nrhs):
                        f"single-threaded")
 
 
+# Request stream of the serving measurement: Poisson arrivals; grid side 128 / 256
+# / 512 / 1024 with probabilities .4 / .3 / .2 / .1, k = side / 6.4, 1-4 right-
+# hand sides; 70 % of the requests reuse an operator already seen for their
+# side, the others bring a new one (k scaled by 1 + 0.05 u, u ~ U(-1, 1)), which
+# forces a full set-up.  Decompositions: 128 -> [2x2] and 256 -> [4x4] (4-cell
+# overlap, rank 8 per interface); 512 -> [2x2, 2x2] and 1024 -> [2x2, 2x2, 2x2]
+# (8-cell overlap, rank 16); 10 oversampling samples; 200 GB device budget.
+SERVING_SIDES = [(128, 0.4, [(2, 2)], [4], [8]), (256, 0.3, [(4, 4)], [4], [8]),
+                 (512, 0.2, [(2, 2), (2, 2)], [8, 8], [16, 16]),
+                 (1024, 0.1, [(2, 2), (2, 2), (2, 2)], [8, 8, 8], [16, 16, 16])]
+
+
+def serving(hh, torch, precision, seconds, rate, drain=30.0, seed=11):
+    """Drives hh_server_* with a seeded request stream for `seconds`, then waits at most `drain`
+    seconds for the requests still queued or running.  Latency = arrival -> result in u (host);
+    requests not finished by then count as unfinished (percentiles treat them as infinitely late)."""
+    import threading
+
+    rng = np.random.default_rng(seed)
+    sched, seen, t, next_id = [], {}, 0.0, 1
+    while t < seconds:
+        t += rng.exponential(1.0 / rate)
+        si = int(rng.choice(len(SERVING_SIDES), p=[x[1] for x in SERVING_SIDES]))
+        side = SERVING_SIDES[si][0]
+        if seen.get(side) and rng.random() < 0.7:
+            oid, k = seen[side][int(rng.integers(len(seen[side])))]
+        else:
+            oid, k = next_id, side / 6.4 * (1.0 + 0.05 * rng.uniform(-1.0, 1.0))
+            next_id += 1
+            seen.setdefault(side, []).append((oid, k))
+        sched.append((t, si, oid, k, int(rng.integers(1, 5))))
+    # device right-hand sides per side (content is immaterial to the timing; CN(0,1))
+    pool = {}
+    for si, (side, _, _, _, _) in enumerate(SERVING_SIDES):
+        n = (side + 1) ** 2
+        g = torch.Generator(device="cuda").manual_seed(seed + si)
+        pool[si] = torch.complex(torch.randn((4, n), device="cuda", dtype=torch.float64, generator=g),
+                                 torch.randn((4, n), device="cuda", dtype=torch.float64, generator=g)) / np.sqrt(2.0)
+    torch.cuda.synchronize()
+    results = [None] * len(sched)
+    srv = hh.Server(200 * 10 ** 9, workers=4, max_batch_rhs=32, precision=precision, gmres_restart=100)
+    tickets = [None] * len(sched)
+    t0 = time.perf_counter()
+    deadline = t0 + seconds + drain
+
+    def collect():
+        pending = 0  # tickets below this index are all collected or not yet submitted
+        while time.perf_counter() < deadline:
+            done = True
+            for i in range(pending, len(sched)):
+                if tickets[i] is None:
+                    done = False
+                    break
+                if results[i] is None:
+                    results[i] = srv.poll(tickets[i])
+                    done = done and results[i] is not None
+            while pending < len(sched) and results[pending] is not None:
+                pending += 1
+            if done and pending == len(sched):
+                return
+            time.sleep(0.002)
+
+    col = threading.Thread(target=collect)
+    col.start()
+    outs = []
+    last = t0
+    for i, (ta, si, oid, k, nr) in enumerate(sched):
+        side, _, m, ov, ranks = SERVING_SIDES[si]
+        now = time.perf_counter() - t0
+        if ta > now:
+            time.sleep(ta - now)
+        f = pool[si][:nr]
+        u = torch.empty_like(f)
+        outs.append(u)
+        tickets[i] = srv.submit(oid, 2, side, k, hh.decomposition(m, ov), ranks, 10, 1000 + oid, f, u, rtol=1e-8,
+                                maxit=1000)
+        if time.perf_counter() - last > 2.0:
+            last = time.perf_counter()
+            print(f"serving: {i + 1}/{len(sched)} submitted, {sum(r is not None for r in results)} done",
+                  file=sys.stderr, flush=True)
+    while col.is_alive():
+        col.join(2.0)
+        print(f"serving: draining, {sum(r is not None for r in results)}/{len(sched)} done", file=sys.stderr,
+              flush=True)
+    wall = time.perf_counter() - t0
+    stats = srv.stats()
+    srv.close()  # drops what is still queued; running batches end first
+    fin = [(x, r) for x, r in zip(sched, results) if r is not None]
+    lat = np.array([r["latency_s"] for _, r in fin] + [np.inf] * (len(sched) - len(fin))) * 1000.0
+    ok = sum(1 for _, r in fin if r["status"] == hh.HH_OK)
+    rhs_done = sum(x[4] for x, _ in fin)
+    by_side = {}
+    for x, r in fin:
+        by_side.setdefault(SERVING_SIDES[x[1]][0], []).append(r["latency_s"] * 1000.0)
+
+    def pct(v, p):
+        q = float(np.percentile(v, p))
+        return round(q, 1) if np.isfinite(q) else None
+
+    return {
+        "requests": len(sched), "finished": len(fin), "converged": ok, "rhs_finished": rhs_done,
+        "stream_s": round(seconds, 2), "wall_s": round(wall, 2), "rhs_per_s": round(rhs_done / wall, 2),
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99)},
+        "latency_p50_ms_by_side": {str(k): round(float(np.percentile(v, 50)), 1) for k, v in sorted(by_side.items())},
+        "mean_batch_rhs": round(float(np.mean([r["batch_rhs"] for _, r in fin])), 2) if fin else None,
+        "cache_hit_rate": round(float(np.mean([r["cache_hit"] for _, r in fin])), 3) if fin else None,
+        "operators_set_up": stats["misses"], "evictions": stats["evictions"],
+    }
+
+
 def copy_calibration(torch):
     n = 1 << 26  # 1 GiB of complex128
     x = torch.ones(n, dtype=torch.complex128, device="cuda")
@@ -273,6 +388,15 @@ def main():
             "phases_ms": {k: round(1000.0 * float(np.mean(v)), 3) for k, v in mres["phases"].items()},
             "solve_only_solves_per_s": round(args.nrhs / float(np.mean(mres["phases"]["solve"])), 3),
             "gmres_iterations_mean": round(float(np.mean(mres["iters"])), 2),
+        }
+    if args.serving_seconds > 0:
+        out["serving"] = {
+            "stream": f"Poisson arrivals at {args.serving_rate:g}/s for {args.serving_seconds:g} s (then "
+                      f"{args.serving_drain:g} s to drain); sides 128/256/512/1024 (p .4/.3/.2/.1), k = side/6.4, "
+                      "1-4 rhs, 70% operator reuse, 200 GB budget, 4 workers, batches <= 32 rhs, GMRES(100) to 1e-8; "
+                      "latency = arrival to result on the host",
+            "fp64": serving(hh, torch, hh.HH_FP64, args.serving_seconds, args.serving_rate, args.serving_drain),
+            "mixed": serving(hh, torch, hh.HH_MIXED, args.serving_seconds, args.serving_rate, args.serving_drain),
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_rhs)

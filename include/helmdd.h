@@ -217,7 +217,10 @@ typedef struct {
 
 hh_status hh_server_create(const hh_server_options* o, hh_server** out);
 /* Queues a request; *ticket identifies it.  HH_EINVAL for an invalid request
- * or an id reused with another shape. */
+ * or an id reused with another shape.  f and u must be ready when the call is
+ * made: the server's own streams do not wait for work queued elsewhere, so any
+ * pending write to f or u (a fill of u included) must have completed.  u is
+ * written once, before the result is handed out by hh_server_wait. */
 hh_status hh_server_submit(hh_server* s, const hh_request* r, uint64_t* ticket);
 /* Waits (timeout_s < 0: without limit) for the request; HH_ESTATE on timeout.
  * A completed ticket is released by the call that returns its result. */
@@ -227,9 +230,10 @@ hh_status hh_server_stats(hh_server* s, int64_t* served, int64_t* misses, int64_
 /* Stops the workers after their running batches; queued requests are dropped. */
 hh_status hh_server_destroy(hh_server* s);
 
-/* Host-side estimate of the device bytes of a prepared operator plus the work
- * space of a solve with nrhs right-hand sides (what the server reserves when
- * it admits a new operator).  rank: per level, as in hh_request. */
+/* Host-side estimate of the peak device bytes of setting up an operator and
+ * solving with nrhs right-hand sides: the prepared operator plus the larger of
+ * the set-up's transient work space and the solve's (what the server reserves
+ * when it admits a new operator).  rank: per level, as in hh_request. */
 hh_status hh_estimate_device_bytes(const hh_operator* A, const hh_decomposition* d, const int32_t* rank,
                                    int32_t oversample, int32_t nrhs, int32_t gmres_restart, int32_t precision,
                                    int64_t* bytes);

@@ -380,6 +380,8 @@ class Server:
         r.u = _dev(u)
         r.rtol = float(rtol)
         r.maxit = int(maxit)
+        # the server's streams do not wait for torch's: finish pending writes to f and u first
+        torch.cuda.current_stream(f.device).synchronize()
         t = ctypes.c_uint64(0)
         _check(_lib.hh_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t)))
         self._keep[t.value] = (f, u)  # tensors stay alive until the result is taken
@@ -389,6 +391,18 @@ class Server:
     def wait(self, ticket: int, timeout_s: float = -1.0) -> dict:
         res = hh_request_result()
         _check(_lib.hh_server_wait(self.handle, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(res)))
+        self._keep.pop(ticket, None)
+        return dict(status=int(res.status), iters=int(res.iters), rel_residual=float(res.rel_residual),
+                    latency_s=float(res.latency_s), queue_s=float(res.queue_s), batch_rhs=int(res.batch_rhs),
+                    cache_hit=bool(res.cache_hit))
+
+    def poll(self, ticket: int):
+        """The result if the request has finished (handed out once), else None."""
+        res = hh_request_result()
+        st = _lib.hh_server_wait(self.handle, ctypes.c_uint64(ticket), 0.0, ctypes.byref(res))
+        if st == HH_ESTATE:
+            return None
+        _check(st)
         self._keep.pop(ticket, None)
         return dict(status=int(res.status), iters=int(res.iters), rel_residual=float(res.rel_residual),
                     latency_s=float(res.latency_s), queue_s=float(res.queue_s), batch_rhs=int(res.batch_rhs),

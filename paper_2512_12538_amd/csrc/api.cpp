@@ -1166,6 +1166,18 @@ hh_status set_stream(hh_ctx* c, hipStream_t s) {
   return HH_OK;
 }
 
+void release_work(hh_ctx* c) {
+  if (!c) return;
+  for (Level& L : c->lv) {
+    for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec, &L.W, &L.RP}) {
+      dfree(c, *b);
+      *b = nullptr;
+    }
+    L.qcap = 0;
+    L.rp_len = 0;
+  }
+}
+
 size_t resident_bytes(const hh_ctx* c) {
   size_t n = 0;
   if (c)
@@ -1173,17 +1185,18 @@ size_t resident_bytes(const hh_ctx* c) {
   return n;
 }
 
-size_t estimate_bytes(const hh_operator* A, const hh_decomposition* d, const int32_t* rank, int32_t oversample,
-                      int32_t q, int32_t restart, int32_t precision) {
-  if (!A || !d || d->levels < 1 || d->levels > 8) return 0;
+Footprint estimate_bytes(const hh_operator* A, const hh_decomposition* d, const int32_t* rank,
+                         int32_t oversample, int32_t restart, int32_t precision) {
+  Footprint f;
+  if (!A || !d || d->levels < 1 || d->levels > 8) return f;
   Geometry g;
-  if (!build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, g).empty()) return 0;
+  if (!build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, g).empty()) return f;
   const double c16 = 16.0;
-  double bytes = 0.0;
+  double op = 0.0, rhs = 0.0, work = 0.0, smax = 1.0;
   // leaf factors: FP64 during the set-up (plus the complex64 copy when mixed)
   double gl = 0.0;
   for (const HBox& b : g.levels[g.depth()]) gl += (double)b.nx() * b.ny() * b.ny();
-  bytes += gl * c16 + (precision == HH_MIXED ? gl * 8.0 : 0.0);
+  op += gl * c16 + (precision == HH_MIXED ? gl * 8.0 : 0.0);
   const double n0 = (double)g.levels[0][0].n();
   for (int l = 0; l <= g.depth(); ++l) {
     double tot = 0.0, csz = 0.0, nc = 0.0;
@@ -1191,18 +1204,20 @@ size_t estimate_bytes(const hh_operator* A, const hh_decomposition* d, const int
       tot += b.n();
       if (l >= 1) {
         const double r = std::min<double>((double)rank[l - 1] * b.n_if, (double)b.iface.size());
-        const double s = std::min<double>(r + oversample, (double)b.iface.size());
-        csz += r * b.n_own() + s * b.iface.size() * 3.0;  // C, Omega / sketch blocks
+        const double sk = std::min<double>(r + oversample, (double)b.iface.size());
+        csz += r * b.n_own() + sk * b.iface.size() * 3.0;  // C, Omega / sketch blocks
         nc += r;
+        smax = std::max(smax, sk);
       }
     }
-    const double qq = std::max(q, 1);
-    bytes += tot * qq * c16 * 6.0;      // level work buffers (R, X, T, E, U, W)
-    bytes += csz * c16 * 2.0;           // coarse blocks and Galerkin products
-    bytes += nc * nc * c16 * 2.0 + nc * qq * c16 * 2.0;
+    op += csz * c16 * 2.0 + nc * nc * c16 * 2.0;  // coarse blocks, Galerkin products, A_c^{-1}
+    work += tot * c16 * 6.0 + nc * c16 * 2.0;     // level work buffers per column
   }
-  bytes += (2.0 * restart + 3.0) * n0 * std::max(q, 1) * c16;  // Krylov bases V, Z and work
-  return (size_t)bytes;
+  rhs = work + (2.0 * restart + 3.0) * n0 * c16;  // plus the Krylov bases V, Z and work
+  f.op = (size_t)op;
+  f.per_rhs = (size_t)rhs;
+  f.setup = (size_t)(work * smax);  // the sketches run smax columns through every level below
+  return f;
 }
 
 }  // namespace helmdd_internal

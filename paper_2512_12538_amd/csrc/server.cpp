@@ -44,6 +44,8 @@ struct OperatorSpec {
   int32_t rank[8] = {0};
   int32_t oversample = 0;
   uint64_t seed = 0;
+  // estimates: prepared operator, its set-up work space, solve work space per right-hand side
+  size_t op_bytes = 0, setup_bytes = 0, rhs_bytes = 0;
 };
 
 struct Entry {
@@ -92,6 +94,7 @@ struct hh_server {
   std::map<uint64_t, Entry> cache;                        // by operator id
   std::map<uint64_t, std::shared_ptr<OperatorSpec>> specs;
   size_t used = 0;  // reserved device bytes (operators + running batches)
+  int preparing = 0;  // workers setting up a new operator
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
   long long served = 0, misses = 0, evictions = 0;
@@ -102,17 +105,33 @@ struct hh_server {
 };
 
 // Oldest queued request whose operator is idle, plus the queued requests of
-// that operator and tolerance that fit the batch width (arrival order).
+// that operator and tolerance that fit the batch width (arrival order).  A
+// request for an operator not yet prepared is passed over while all other
+// workers are already preparing operators, so that prepared operators keep
+// being served.  The batch width is capped so that its work space takes at
+// most half the budget.
 bool hh_server::take_batch(std::unique_lock<std::mutex>&, std::vector<Request*>& batch, uint64_t& id) {
   for (auto it = queue.begin(); it != queue.end(); ++it) {
     Request* r = *it;
     auto ce = cache.find(r->id);
     if (ce != cache.end() && ce->second.busy) continue;
+    const bool miss = ce == cache.end() || !ce->second.ctx;
+    if (miss && o.workers > 1 && preparing >= o.workers - 1) continue;
+    OperatorSpec& sp = *specs[r->id];
+    if (sp.rhs_bytes == 0) {
+      const helmdd_internal::Footprint fp =
+          helmdd_internal::estimate_bytes(&sp.op, &sp.d, sp.rank, sp.oversample, o.gmres_restart, o.precision);
+      sp.op_bytes = fp.op;
+      sp.setup_bytes = fp.setup;
+      sp.rhs_bytes = std::max<size_t>(fp.per_rhs, 1);
+    }
+    const long long cap = std::max<long long>(1, (long long)(o.budget_bytes / 2) / (long long)sp.rhs_bytes);
+    const int wmax = (int)std::min<long long>(o.max_batch_rhs, std::max<long long>(cap, r->nrhs));
     id = r->id;
     int width = 0;
     for (auto jt = it; jt != queue.end();) {
       Request* x = *jt;
-      if (x->id == id && x->rtol == r->rtol && x->maxit == r->maxit && width + x->nrhs <= o.max_batch_rhs) {
+      if (x->id == id && x->rtol == r->rtol && x->maxit == r->maxit && width + x->nrhs <= wmax) {
         width += x->nrhs;
         batch.push_back(x);
         jt = queue.erase(jt);
@@ -183,6 +202,7 @@ hh_status hh_server::prepare(Entry& e, hipStream_t s) {
     hh_destroy(c);
     return st;
   }
+  helmdd_internal::release_work(c);  // cached operators keep factors and coarse data only
   e.ctx = c;
   e.bytes = helmdd_internal::resident_bytes(c);
   return HH_OK;
@@ -204,13 +224,10 @@ void hh_server::worker(int w) {
     int q = 0;
     for (Request* r : batch) q += r->nrhs;
     const bool hit = e.ctx != nullptr;
-    // admission: the operator (on a miss) and this batch's work space
-    const size_t est_op = hit ? 0 : helmdd_internal::estimate_bytes(&sp.op, &sp.d, sp.rank, sp.oversample, 0,
-                                                                     o.gmres_restart, o.precision);
-    const size_t est_run = helmdd_internal::estimate_bytes(&sp.op, &sp.d, sp.rank, sp.oversample, q, o.gmres_restart,
-                                                           o.precision) -
-                           helmdd_internal::estimate_bytes(&sp.op, &sp.d, sp.rank, sp.oversample, 0,
-                                                           o.gmres_restart, o.precision);
+    // admission: the operator (on a miss) and this batch's work space; the
+    // set-up work space is returned before the solve's is taken
+    const size_t est_run = sp.rhs_bytes * (size_t)q;
+    const size_t est_op = hit ? 0 : sp.op_bytes + (sp.setup_bytes > est_run ? sp.setup_bytes - est_run : 0);
     const size_t need = est_op + est_run;
     hh_status st = HH_OK;
     bool charged = false;
@@ -246,6 +263,7 @@ void hh_server::worker(int w) {
     if (st == HH_OK) {
       used += need;
       charged = true;
+      if (!hit) ++preparing;
     }
     const Clock::time_point t_start = Clock::now();
     for (Request* r : batch) r->start = t_start;
@@ -257,6 +275,7 @@ void hh_server::worker(int w) {
       ++misses;
       // keep the measured footprint reserved instead of the estimate
       used -= est_op;
+      --preparing;
       if (st == HH_OK) {
         used += e.bytes;
         e.reserved = e.bytes;
@@ -293,6 +312,7 @@ void hh_server::worker(int w) {
           }
           if (hipStreamSynchronize(s) != hipSuccess) st = HH_EDEVICE;
         }
+        helmdd_internal::release_work(e.ctx);
       }
       if (F) devpool::release(F, vb, s);
       if (U) devpool::release(U, vb, s);
@@ -448,10 +468,10 @@ hh_status hh_estimate_device_bytes(const hh_operator* A, const hh_decomposition*
                                    int32_t oversample, int32_t nrhs, int32_t gmres_restart, int32_t precision,
                                    int64_t* bytes) {
   if (!A || !d || !rank || !bytes || nrhs < 0) return HH_EINVAL;
-  const size_t b = helmdd_internal::estimate_bytes(A, d, rank, oversample, nrhs,
-                                                   gmres_restart > 0 ? gmres_restart : 50, precision);
-  if (b == 0) return HH_EINVAL;
-  *bytes = (int64_t)b;
+  const helmdd_internal::Footprint f =
+      helmdd_internal::estimate_bytes(A, d, rank, oversample, gmres_restart > 0 ? gmres_restart : 50, precision);
+  if (f.op == 0) return HH_EINVAL;
+  *bytes = (int64_t)(f.op + std::max(f.setup, f.per_rhs * (size_t)nrhs));
   return HH_OK;
 }
 

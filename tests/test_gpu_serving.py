@@ -95,6 +95,7 @@ def test_served_result_equals_direct_solve(hh):
     oid = 12
     N, k, m, ov, ranks = OPS[oid]
     (u_srv,), (res,), _ = _serve(hh, [(oid, 2, 555)], workers=1, one_at_a_time=True)
+    assert res["status"] == hh.HH_OK
     ctx = hh.hh_setup(2, N, k, hh.decomposition(m, ov))
     try:
         for level in range(len(m), 0, -1):
@@ -114,7 +115,8 @@ def test_served_result_equals_direct_solve(hh):
 
 def test_budget_evicts_idle_operators_and_refuses_oversize(hh):
     reqs = [(21, 1, 900), (22, 1, 901), (21, 1, 902), (22, 1, 903)]
-    ref, _, _ = _serve(hh, reqs, workers=1, one_at_a_time=True)
+    ref, rr, _ = _serve(hh, reqs, workers=1, one_at_a_time=True)
+    assert all(r["status"] == hh.HH_OK for r in rr)
     _, _, st1 = _serve(hh, reqs[:1], workers=1, one_at_a_time=True)
     resident = st1["reserved_bytes"]  # one prepared operator, no batch running
     N, k, m, ov, ranks = TWINS[21]
