@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz
 VALU_PEAK_TFS = 78.6
 CFG = dict(N=256, k=40.0, m=[(4, 4)], overlap=[4], rank=8, oversample=10, rtol=1e-8, maxit=500, restart=50)
-FAMILY = {0: "k_leaf_solve (block-tridiagonal sweeps)", 1: "k_basis_update (Gram-Schmidt)",
+FAMILY = {0: "k_sweep (leaf block-tridiagonal solve, phase 1 + phase 2)", 1: "k_basis_update (Gram-Schmidt)",
           2: "k_dot_partial (Gram-Schmidt inner products)"}
 
 
@@ -119,12 +119,12 @@ def run_gpu(hh, torch, nrhs, precision, steps, warmup, profile):
     return dict(wall=wall, phases=phases, lat=lat, iters=iters, u=u, f=f, prof=prof)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_leaf_solve_helm2d_n256_k40_4x4.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_12538_amd", "csrc", f) for f in ("k_leaf.hip", "common.h")]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_helm2d_n256_k40_4x4.md")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_12538_amd", "csrc", f) for f in ("k_sweep.hip", "common.h")]
 
 
 def measured_traffic(nrhs, precision):
-    """HBM bytes per leaf-solve launch from the committed FETCH_SIZE / WRITE_SIZE passes,
+    """HBM bytes per leaf solve (phase 1 + phase 2 dispatches) from the committed FETCH_SIZE / WRITE_SIZE passes,
     scaled by the copy calibration; None when the kernel source or the workload differs."""
     import hashlib
 

@@ -22,6 +22,15 @@ inline int nblocks(long long n) {
 }
 
 constexpr int EPT = CHUNK / TB;  // elements per thread and pass over a block's chunk
+constexpr int NXCD = 8;          // XCDs; hardware block i runs on XCD i mod 8
+
+// Krylov basis loads: the basis of a batch is far larger than the caches and
+// each vector is read once per pass, so these loads bypass them.
+typedef double d2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ldnt(const c128* p) {
+  const d2v v = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(p));
+  return mk(v.x, v.y);
+}
 
 // ---- wave reductions without LDS: gfx950 permlane32/permlane16 swaps for
 // lane bits 5 and 4, DPP for bits 0..3.
@@ -119,16 +128,23 @@ __device__ __forceinline__ double block_sum1(double v, double* red) {
   return r;
 }
 
-// partial[((k*q + b)*NB + blk] = sum over the block's chunk of conj(V_k[b]) W[b],
+// partial[blk*S + k*q + b] = sum over the block's chunk of conj(V_k[b]) W[b],
 // KG consecutive k per block so that W is read once per KG products; each
 // thread keeps KG x EPT basis loads in flight.  With wnorm, the first group
 // also accumulates |W[b]|^2 into row nk.  Columns with skip[b] == 0 are left
-// untouched (skip may be null).
-__global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, int NB, const c128* __restrict__ V,
+// untouched (skip may be null).  S = (nk + wnorm) * q: the final sums read
+// consecutive entries per block.  One-dimensional XCD-aware grid: logical
+// block ((b * NB + blk) * NKG + kg), contiguous per XCD, so the groups that
+// share a chunk of W run on one XCD and read it from its L2.
+__global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, int NB, int S, const c128* __restrict__ V,
                                                     long long vstride, const c128* __restrict__ W,
                                                     c128* __restrict__ partial, int wnorm,
                                                     const int* __restrict__ skip) {
-  const int blk = blockIdx.x, k0 = blockIdx.y * KG, b = blockIdx.z;
+  const int nkg = (nk + KG - 1) / KG;
+  const int lb = (blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
+  if (lb >= NB * nkg * q) return;
+  const int kg = lb % nkg, t = lb / nkg;
+  const int blk = t % NB, k0 = kg * KG, b = t / NB;
   if (skip && !skip[b]) return;
   const long long per = (n + NB - 1) / NB;
   const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
@@ -153,7 +169,7 @@ __global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, 
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const long long i = i0 + threadIdx.x + (long long)e * TB;
-        vv[t][e] = (t < kn && i < hi) ? vb[(k0 + t) * vstride + i] : mk(0.0, 0.0);
+        vv[t][e] = (t < kn && i < hi) ? ldnt(vb + (k0 + t) * vstride + i) : mk(0.0, 0.0);
       }
 #pragma unroll
     for (int t = 0; t < KG; ++t)
@@ -166,10 +182,10 @@ __global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, 
   }
   __shared__ double2 red[(TB / 64) * KG];
   const double2 r = block_sum8(acc, red);
-  if (threadIdx.x < kn) partial[((long long)(k0 + threadIdx.x) * q + b) * NB + blk] = r;
+  if (threadIdx.x < kn) partial[(long long)blk * S + (k0 + threadIdx.x) * q + b] = r;
   if (wn) {
     const double rn = block_sum1(nw, reinterpret_cast<double*>(red));
-    if (threadIdx.x == 0) partial[((long long)nk * q + b) * NB + blk] = mk(rn, 0.0);
+    if (threadIdx.x == 0) partial[(long long)blk * S + nk * q + b] = mk(rn, 0.0);
   }
 }
 
@@ -179,7 +195,7 @@ __global__ void k_dot_final(int nkq, int q, int NB, const c128* __restrict__ par
   if (t >= nkq) return;
   if (skip && !skip[t % q]) return;
   double2 acc = mk(0.0, 0.0);
-  for (int blk = 0; blk < NB; ++blk) acc = cadd(acc, partial[(long long)t * NB + blk]);
+  for (int blk = 0; blk < NB; ++blk) acc = cadd(acc, partial[(long long)blk * nkq + t]);
   out[t] = acc;
 }
 
@@ -213,7 +229,7 @@ __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n,
 #pragma unroll
         for (int e = 0; e < EPT; ++e) {
           const long long i = i0 + threadIdx.x + (long long)e * TB;
-          vv[t][e] = i < hi ? vb[(k + t) * vstride + i] : mk(0.0, 0.0);
+          vv[t][e] = i < hi ? ldnt(vb + (k + t) * vstride + i) : mk(0.0, 0.0);
         }
 #pragma unroll
       for (int t = 0; t < KG; ++t) {
@@ -227,7 +243,7 @@ __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n,
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const long long i = i0 + threadIdx.x + (long long)e * TB;
-        const double2 v = i < hi ? vb[k * vstride + i] : mk(0.0, 0.0);
+        const double2 v = i < hi ? ldnt(vb + k * vstride + i) : mk(0.0, 0.0);
         w[e] = csub(w[e], cmul(v, hk));
       }
     }
@@ -243,7 +259,7 @@ __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n,
   if (npart) {
     __shared__ double red[TB / 64];
     const double r = block_sum1(nrm, red);
-    if (threadIdx.x == 0) npart[(long long)b * NB + blk] = mk(r, 0.0);
+    if (threadIdx.x == 0) npart[(long long)blk * q + b] = mk(r, 0.0);
   }
 }
 
@@ -400,9 +416,12 @@ hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long 
                            c128* partial, c128* out, hipStream_t s, int wnorm, const int* skip) {
   if (nk <= 0 || q <= 0) return hipSuccess;
   const int NB = nblocks(n);
-  hipLaunchKernelGGL(k_dot_partial, dim3(NB, (nk + KG - 1) / KG, q), dim3(TB), 0, s, nk, q, n, NB, V, vstride, W,
-                     partial, wnorm, skip);
   const int nkq = (nk + (wnorm ? 1 : 0)) * q;
+  const long long nlog = (long long)NB * ((nk + KG - 1) / KG) * q;
+  if (nlog > (1LL << 30)) return hipErrorInvalidValue;
+  const long long grid = (nlog + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)grid), dim3(TB), 0, s, nk, q, n, NB, nkq, V, vstride, W, partial,
+                     wnorm, skip);
   hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, q, NB, partial, out, skip);
   return hipGetLastError();
 }

@@ -133,13 +133,15 @@ struct SlotMap {
   }
 };
 
-// phase 1: outer lines towards the middle; phase 2: middle line and back-substitution
-template <typename T, int QB, int TM, int R, int NW, bool PF>
+// PHASE 1: outer lines towards the middle; PHASE 2: middle line and
+// back-substitution (a template argument, so profiles list the phases apart)
+template <typename T, int QB, int TM, int R, int NW, bool PF, int PHASE>
 __global__ void __launch_bounds__(64 * NW)
-    k_sweep(OpDev op, const BoxDev* __restrict__ leaves, int nunit, int nchunk, int q, int phase,
+    k_sweep(OpDev op, const BoxDev* __restrict__ leaves, int nunit, int nchunk, int q,
             const typename cvec<T>::type* __restrict__ G, const c128* __restrict__ rhs, c128* __restrict__ x,
             c128* __restrict__ edge, int edge_ld, const BoxDev* __restrict__ par, c128* __restrict__ out) {
   typedef typename cvec<T>::type CT;
+  constexpr int phase = PHASE;
   constexpr int NT = 64 * NW, RG = 8 * NW, M0 = TM * QB;
   constexpr int YS = R * QB + 1;  // LDS stride of a column slice (odd: slices start on different banks)
   typedef SlotMap<M0> SM;
@@ -338,13 +340,13 @@ hipError_t launch_sweep(const OpDev& op, const BoxDev* leaves, int nleaf, int q,
                         hipStream_t s) {
   const int nchunk = (q + QB - 1) / QB, nunit = 2 * nleaf;
   const dim3 grid(nunit * nchunk), block(64 * NW);
-  for (int phase = 1; phase <= 2; ++phase) {
-    hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF>), grid, block, 0, s, op, leaves, nunit, nchunk, q, phase, G, rhs,
-                       x, edge, edge_ld, par, out);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 1>), grid, block, 0, s, op, leaves, nunit, nchunk, q, G, rhs, x,
+                     edge, edge_ld, par, out);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 2>), grid, block, 0, s, op, leaves, nunit, nchunk, q, G, rhs, x,
+                     edge, edge_ld, par, out);
+  return hipGetLastError();
 }
 
 // Column count QB per work-group: enough work-groups to cover the chip, and

@@ -10,13 +10,23 @@ constexpr int TB = 256;
 
 // y = A_box x (mode 0) or y = b - A_box x (mode 1): one thread per node of a
 // box, its five stencil coefficients formed once and applied to QG columns.
-constexpr int QG = 16;
+// The grid is one-dimensional and XCD-aware: the hardware places block i on
+// XCD i mod 8, and logical block (i mod 8) * (gridDim.x / 8) + i / 8 makes
+// every XCD run a contiguous range of node blocks, so the rows above and below
+// a block (read by its stencil) sit in the same L2 as the block that loads
+// them first.  Logical order: node block fastest, then box, then column group.
+constexpr int QG = 2;
+constexpr int NXCD = 8;
 
-__global__ void __launch_bounds__(TB) k_apply_box(OpDev op, const BoxDev* __restrict__ boxes, int q,
-                                                  const c128* __restrict__ x, const c128* __restrict__ b,
-                                                  c128* __restrict__ y, int mode) {
-  const BoxDev B = boxes[blockIdx.y];
-  const int l = blockIdx.x * TB + threadIdx.x;
+__global__ void __launch_bounds__(TB) k_apply_box(OpDev op, const BoxDev* __restrict__ boxes, int nbox, int gxb,
+                                                  int nlog, int q, const c128* __restrict__ x,
+                                                  const c128* __restrict__ b, c128* __restrict__ y, int mode) {
+  const int lb = (blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
+  if (lb >= nlog) return;
+  const int nb = lb % gxb, t = lb / gxb;
+  const int box = t % nbox, cg = t / nbox;
+  const BoxDev B = boxes[box];
+  const int l = nb * TB + threadIdx.x;
   if (l >= B.n) return;
   const int a = l / B.ny, c = l - a * B.ny;
   const int p = B.p0 + a, qq = B.q0 + c;
@@ -29,8 +39,8 @@ __global__ void __launch_bounds__(TB) k_apply_box(OpDev op, const BoxDev* __rest
   const double2 cn = hn ? stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, qq, 0, 1) : z;
   // absent neighbours read the node itself with a zero coefficient
   const int lw = hw ? l - B.ny : l, le = he ? l + B.ny : l, ls = hs ? l - 1 : l, ln = hn ? l + 1 : l;
-  const int c0 = blockIdx.z * QG, c1 = c0 + QG < q ? c0 + QG : q;
-#pragma unroll 4
+  const int c0 = cg * QG, c1 = c0 + QG < q ? c0 + QG : q;
+#pragma unroll
   for (int col = c0; col < c1; ++col) {
     const c128* xb = x + B.voff * q + (long long)col * B.n;
     double2 v = cmul(cd, xb[l]);
@@ -136,9 +146,13 @@ inline int grid_for(long long n, int cap = 4096) {
 
 hipError_t launch_apply_box(const OpDev& op, const BoxDev* boxes, int nbox, int max_n, int q,
                             const c128* x, const c128* b, c128* y, int mode, hipStream_t s) {
-  if (nbox <= 0 || q <= 0) return hipSuccess;
-  dim3 grid((max_n + TB - 1) / TB, nbox, (q + QG - 1) / QG);
-  hipLaunchKernelGGL(k_apply_box, grid, dim3(TB), 0, s, op, boxes, q, x, b, y, mode);
+  if (nbox <= 0 || q <= 0 || max_n <= 0) return hipSuccess;
+  const int gxb = (max_n + TB - 1) / TB;
+  const long long nlog = (long long)gxb * nbox * ((q + QG - 1) / QG);
+  if (nlog > (1LL << 30)) return hipErrorInvalidValue;
+  const long long grid = (nlog + NXCD - 1) / NXCD * NXCD;
+  hipLaunchKernelGGL(k_apply_box, dim3((unsigned)grid), dim3(TB), 0, s, op, boxes, nbox, gxb, (int)nlog, q, x, b, y,
+                     mode);
   return hipGetLastError();
 }
 
