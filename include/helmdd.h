@@ -101,6 +101,24 @@ typedef struct {
  * zero pivot. */
 hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_options* o, hh_ctx** out);
 
+/* Independent problems in one context (the local problems of every level of
+ * every problem go into the same launches).  A[p], d[p] (p < nprob): operator
+ * and decomposition of problem p; all problems share dim and the number of
+ * levels.  The boxes of a level are numbered problem by problem, so per-box
+ * arrays of the other calls (hh_level_info, omega of hh_build_coarse) list
+ * problem 0's boxes first.  Whole-domain vectors of the other calls hold, per
+ * problem in order, its nrhs columns: [p][nrhs][n_p] with n_p = (N_p+1)^dim
+ * (hh_problem_layout gives the offsets); hh_solve's info has nprob * nrhs
+ * entries, problem-major.  Same errors as hh_setup (HH_EINVAL also when the
+ * problems differ in dim or depth).  hh_setup is hh_setup_batch with nprob = 1. */
+hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposition* d, const hh_options* o,
+                         hh_ctx** out);
+
+/* nprob, and per problem its node count n_p and the offset (in complex entries,
+ * per right-hand side) of its block: problem p's column c starts at
+ * nrhs * offset[p] + c * n_p.  Arrays have nprob entries; any may be null. */
+hh_status hh_problem_layout(const hh_ctx* c, int32_t* nprob, int64_t* n_nodes, int64_t* offset);
+
 /* Number of boxes of a level (0 = the whole domain) and, per box, its interface
  * size m_in, coarse rank r_i = min(rank_per_interface * n_if, m_in) and sketch
  * width s_i = min(r_i + oversample, m_in) (n_if = interface sides of the box).
@@ -122,10 +140,12 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank_per_interface, 
 
 /* Solves A u = b for nrhs right-hand sides: b = f + impedance data g (2D:
  * (boundary edges at the node)/2 * g/h, 1D: g/h at the end nodes).
- * f, g, u: device c128 arrays [nrhs][(N+1)^dim]; g may be null (g = 0).
+ * f, g, u: device c128 arrays [nrhs][(N+1)^dim] (a batch: per problem, see
+ * hh_setup_batch); g may be null (g = 0).
  * u0 = 0; the outer loop (hh_options.outer) stops when
  * ||b - A u||_2 / ||b||_2 < rtol or after maxit preconditioner applications
- * (rtol = 0 runs exactly maxit).  info: host array of nrhs entries or null.
+ * (rtol = 0 runs exactly maxit).  info: host array of nrhs entries (a batch:
+ * nprob * nrhs) or null.
  * HH_ENOTCONV if some right-hand side did not converge. */
 hh_status hh_solve(hh_ctx* c, int32_t nrhs, const void* f, const void* g, void* u, double rtol, int32_t maxit,
                    hh_solve_info* info);

@@ -16,7 +16,7 @@ import numpy as np
 import torch  # load torch's HIP runtime first so the library shares it
 
 __all__ = [
-    "HelmddError", "hh_setup", "hh_level_info", "hh_build_coarse", "hh_solve", "hh_apply_operator",
+    "HelmddError", "hh_setup", "hh_setup_batch", "hh_level_info", "hh_build_coarse", "hh_solve", "hh_apply_operator",
     "hh_precondition", "hh_get_coarse", "hh_get_basis", "hh_destroy", "decomposition", "library_path",
     "HH_FP64", "HH_MIXED", "HH_STATIONARY", "HH_GMRES", "Context", "hh_profile", "hh_profile_read",
 ]
@@ -93,6 +93,9 @@ def _load():
     sig = {
         "hh_setup": [ctypes.POINTER(hh_operator), ctypes.POINTER(hh_decomposition), ctypes.POINTER(hh_options),
                      ctypes.POINTER(P)],
+        "hh_setup_batch": [i32, ctypes.POINTER(hh_operator), ctypes.POINTER(hh_decomposition),
+                           ctypes.POINTER(hh_options), ctypes.POINTER(P)],
+        "hh_problem_layout": [P, P, P, P],
         "hh_level_info": [P, i32, i32, i32, P, P, P, P],
         "hh_build_coarse": [P, i32, i32, i32, P],
         "hh_solve": [P, i32, P, P, P, ctypes.c_double, i32, P],
@@ -168,13 +171,30 @@ def decomposition(m, overlap, inner_iters=None) -> hh_decomposition:
 
 
 class Context:
-    """Handle of a solver context plus the sizes the binding checks arrays against."""
+    """Handle of a solver context plus the sizes the binding checks arrays against.
 
-    def __init__(self, handle: ctypes.c_void_p, dim: int, n_cells: int):
+    A batch context (hh_setup_batch) holds several problems; ``n`` is then the
+    total node count and ``n_nodes``/``offsets`` give problem p's block: its
+    column c of an nrhs-column vector starts at nrhs * offsets[p] + c * n_nodes[p]."""
+
+    def __init__(self, handle: ctypes.c_void_p, dim: int, n_cells):
         self.handle = handle
         self.dim = dim
         self.n_cells = n_cells
-        self.n = (n_cells + 1) ** dim
+        cells = list(n_cells) if isinstance(n_cells, (list, tuple)) else [n_cells]
+        self.n_nodes = [(nc + 1) ** dim for nc in cells]
+        self.offsets = list(np.cumsum([0] + self.n_nodes[:-1]))
+        self.nprob = len(cells)
+        self.n = int(sum(self.n_nodes))
+
+    def pack(self, blocks):
+        """One whole-domain tensor from per-problem tensors [nrhs][n_p] (same nrhs)."""
+        return torch.cat([b.reshape(-1) for b in blocks])
+
+    def unpack(self, t, nrhs: int):
+        """Per-problem views [nrhs][n_p] of a whole-domain tensor."""
+        flat = t.reshape(-1)
+        return [flat[nrhs * o: nrhs * (o + n)].view(nrhs, n) for o, n in zip(self.offsets, self.n_nodes)]
 
     @property
     def _as_parameter_(self):
@@ -217,6 +237,49 @@ def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int
     return Context(ctx, dim, n_cells)
 
 
+def hh_setup_batch(dim: int, problems, precision: int = HH_FP64, outer: int = HH_GMRES, gmres_restart: int = 50,
+                   stream: torch.cuda.Stream | None = None, full_reorth: bool = False):
+    """Independent problems in one context.  ``problems``: sequence of (n_cells, k, decomposition),
+    k a float or a host array of node wavenumbers.  Returns a Context (see Context.pack/unpack)."""
+    nprob = len(problems)
+    ops = (hh_operator * nprob)()
+    decs = (hh_decomposition * nprob)()
+    keep = []
+    for p, (n_cells, k, decomp) in enumerate(problems):
+        ops[p].dim = dim
+        ops[p].n_cells = int(n_cells)
+        if np.isscalar(k):
+            ops[p].k = None
+            ops[p].k_const = float(k)
+        else:
+            arr = np.ascontiguousarray(k, dtype=np.float64)
+            if arr.size != (n_cells + 1) ** dim:
+                raise ValueError("k must hold one value per node")
+            keep.append(arr)
+            ops[p].k = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            ops[p].k_const = 0.0
+        decs[p] = decomp
+    opts = hh_options()
+    opts.precision = precision
+    opts.outer = outer
+    opts.gmres_restart = gmres_restart
+    opts.full_reorth = 1 if full_reorth else 0
+    st = stream if stream is not None else torch.cuda.current_stream()
+    opts.stream = ctypes.c_void_p(st.cuda_stream)
+    ctx = ctypes.c_void_p()
+    _check(_lib.hh_setup_batch(nprob, ops, decs, ctypes.byref(opts), ctypes.byref(ctx)))
+    del keep
+    c = Context(ctx, dim, [int(pr[0]) for pr in problems])
+    nn = np.zeros(nprob, np.int64)
+    off = np.zeros(nprob, np.int64)
+    _check(_lib.hh_problem_layout(c, None, nn.ctypes.data_as(ctypes.c_void_p), off.ctypes.data_as(ctypes.c_void_p)),
+           c)
+    if list(nn) != c.n_nodes or list(off) != c.offsets:
+        hh_destroy(c)
+        raise RuntimeError("problem layout differs from the binding's")
+    return c
+
+
 def hh_level_info(ctx, level: int, rank: int = 0, oversample: int = 0):
     """(m_in, r, s) arrays of the boxes of a level."""
     nb = ctypes.c_int32()
@@ -240,15 +303,17 @@ def hh_build_coarse(ctx, level: int, rank: int, oversample: int, omega: torch.Te
 
 def hh_solve(ctx, f: torch.Tensor, u: torch.Tensor, rtol: float, maxit: int, g: torch.Tensor | None = None,
              raise_on_notconv: bool = False):
-    """Solves for the rows of f (nrhs x n) into u.  Returns a list of (iters, converged, rel_residual)."""
+    """Solves for the rows of f (nrhs x n) into u.  Returns a list of (iters, converged, rel_residual),
+    one per (problem, right-hand side), problem-major."""
     nrhs = _vectors(ctx, f, "f")
     if u.numel() != f.numel() or (g is not None and g.numel() != f.numel()):
         raise ValueError("u (and g) must match f")
-    info = (hh_solve_info * nrhs)()
+    nsys = nrhs * ctx.nprob
+    info = (hh_solve_info * nsys)()
     st = _lib.hh_solve(ctx, nrhs, _dev(f), _dev(g), _dev(u), float(rtol), int(maxit), info)
     if st != HH_OK and not (st == HH_ENOTCONV and not raise_on_notconv):
         _check(st, ctx)
-    return [(info[i].iters, bool(info[i].converged), info[i].rel_residual) for i in range(nrhs)]
+    return [(info[i].iters, bool(info[i].converged), info[i].rel_residual) for i in range(nsys)]
 
 
 def hh_apply_operator(ctx, x: torch.Tensor, y: torch.Tensor, b: torch.Tensor | None = None) -> None:

@@ -27,6 +27,13 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// Leaves of one kernel shape: order[start .. start + count) of a level's
+// leaf-order array, widths at most max_ny.
+struct LeafGroup {
+  int key = 0, start = 0, count = 0, max_ny = 0;
+  int qb = 0, qb_q = 0;  // sweep: right-hand sides per work-group chosen for qb_q columns (0: not tuned)
+};
+
 struct Level {
   int nbox = 0;
   std::vector<BoxDev> hb;
@@ -69,6 +76,9 @@ struct Level {
   c128* W = nullptr;   // leaf level: the two half-sweep end lines per box (2 nbox q max_ny)
   c128* RP = nullptr;  // parent levels: chunk partial sums of the coarse restriction
   long long rp_len = 0;
+  // leaf level: leaves grouped by sweep shape and by factorisation kernel
+  std::vector<LeafGroup> sweep_groups, factor_groups;
+  int *d_sweep_order = nullptr, *d_factor_order = nullptr;
 };
 
 }  // namespace
@@ -81,9 +91,17 @@ struct hh_ctx {
   int outer = HH_GMRES;
   int restart = 50;
   double reorth_eta = 0.125;
-  Geometry geo;
-  OpDev op{};
+  Geometry geo;             // all problems of the batch, merged level by level
+  int nprob = 1;
+  std::vector<OpDev> hops;  // per problem (k points into d_k)
+  OpDev* d_ops = nullptr;
   double* d_k = nullptr;
+  // outer-loop systems (problem, right-hand side) for sg_q right-hand sides
+  SegDev sg;
+  int sg_q = 0;
+  long long* d_seg_off = nullptr;
+  int *d_seg_len = nullptr, *d_seg_nb = nullptr;
+  int2* d_seg_chunk = nullptr;
   int L = 0;
   std::vector<int> inner;
   std::vector<Level> lv;
@@ -178,6 +196,27 @@ hh_status sync(hh_ctx* c) {
 }
 
 hh_status push_boxes(hh_ctx* c, Level& L) { return upload(c, &L.d, L.hb); }
+
+// Groups the leaves by key(ny) (ascending key, leaves ascending within a group).
+template <typename F>
+hh_status group_leaves(hh_ctx* c, const Level& L, F key, std::vector<LeafGroup>& groups, int** d_order) {
+  std::vector<int> idx(L.nbox);
+  for (int i = 0; i < L.nbox; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return key(L.hb[a].ny) < key(L.hb[b].ny); });
+  groups.clear();
+  for (int t = 0; t < L.nbox; ++t) {
+    const int k = key(L.hb[idx[t]].ny);
+    if (groups.empty() || groups.back().key != k) {
+      LeafGroup g;
+      g.key = k;
+      g.start = t;
+      groups.push_back(g);
+    }
+    groups.back().count += 1;
+    groups.back().max_ny = std::max(groups.back().max_ny, L.hb[idx[t]].ny);
+  }
+  return upload(c, d_order, idx);
+}
 
 // Grow the work buffers of levels lo..L to hold q columns.
 hh_status ensure_work(hh_ctx* c, int lo, int q) {
@@ -309,7 +348,7 @@ hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
     HH_CHECK(launch_scatter_owned(Ch.d, Ch.nbox, Ch.max_own, P.d, q, Ch.X, out, c->stream));
   }
   if (P.has_coarse) {
-    HH_CHECK(launch_apply_box(c->op, P.d, P.nbox, P.max_n, q, out, r, P.T, 1, c->stream));
+    HH_CHECK(launch_apply_box(c->d_ops, P.d, P.nbox, P.max_n, q, out, r, P.T, 1, c->stream));
     if (P.rp_len < restrict_workspace(Ch.nbox, Ch.max_own, Ch.rmax, q))
       return fail(c, HH_EDEVICE, "coarse restriction workspace smaller than the launch needs");
     HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, Ch.max_own, P.d, P.dp, Ch.rmax, q, Ch.C, P.T, P.RP, P.cvec,
@@ -328,12 +367,16 @@ hh_status leaf_solve(hh_ctx* c, int q, const c128* rhs, c128* x, const BoxDev* p
   if (c->prof) leaf_solve_cost(Lv, q, c->precision == HH_MIXED ? 8 : 16, bytes, flops);
   ProfScope ps(c, 0, bytes, flops);
   if (Lv.qcap < q) return fail(c, HH_EDEVICE, "leaf solve work space smaller than the launch needs");
-  if (c->precision == HH_MIXED) {
-    HH_CHECK(launch_leaf_solve<float>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G32, rhs, x, Lv.W, par, out,
-                                      c->stream));
-  } else {
-    HH_CHECK(launch_leaf_solve<double>(c->op, Lv.d, Lv.nbox, Lv.max_ny, q, c->G, rhs, x, Lv.W, par, out,
-                                       c->stream));
+  for (LeafGroup& g : Lv.sweep_groups) {
+    const int* lidx = Lv.d_sweep_order + g.start;
+    const int qb = g.qb_q == q ? g.qb : 0;
+    if (c->precision == HH_MIXED) {
+      HH_CHECK(launch_leaf_solve<float>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G32, rhs, x, Lv.W,
+                                        par, out, c->stream));
+    } else {
+      HH_CHECK(launch_leaf_solve<double>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G, rhs, x, Lv.W,
+                                         par, out, c->stream));
+    }
   }
   return HH_OK;
 }
@@ -346,7 +389,7 @@ hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x) {
   const int ni = std::max(1, c->inner[l]);
   HH_TRY(two_level(c, l, q, rhs, x));
   for (int it = 1; it < ni; ++it) {
-    HH_CHECK(launch_apply_box(c->op, Lv.d, Lv.nbox, Lv.max_n, q, x, rhs, Lv.E, 1, c->stream));
+    HH_CHECK(launch_apply_box(c->d_ops, Lv.d, Lv.nbox, Lv.max_n, q, x, rhs, Lv.E, 1, c->stream));
     HH_TRY(two_level(c, l, q, Lv.E, Lv.U));
     HH_CHECK(launch_add_masked(Lv.U, x, (long long)Lv.total * q, 1, nullptr, c->stream));
   }
@@ -365,15 +408,51 @@ hh_status check_built(hh_ctx* c) {
   return HH_OK;
 }
 
-// Device norms of q columns of length n: out[b] = ||x_b||_2 on the host.
-hh_status norms(hh_ctx* c, int q, long long n, const c128* x, c128* dtmp, std::vector<double>& out) {
-  HH_TRY(ensure_partial(c, (size_t)q * multidot_nblocks(n)));
-  HH_CHECK(launch_multidot(1, q, n, x, 0, x, c->d_partial, dtmp, c->stream));
-  std::vector<c128> h(q);
-  HH_CHECK(hipMemcpyAsync(h.data(), dtmp, q * sizeof(c128), hipMemcpyDeviceToHost, c->stream));
+// Outer-loop systems for q right-hand sides: system b = p q + c is column c of
+// problem p, the segment of level-0 box p that holds it.
+hh_status ensure_segs(hh_ctx* c, int q) {
+  if (c->sg_q == q) return HH_OK;
+  const Level& R = c->lv[0];
+  const int S = R.nbox * q;
+  std::vector<long long> off(S);
+  std::vector<int> len(S), nb(S);
+  std::vector<int2> ch;
+  int nbmax = 0;
+  for (int p = 0; p < R.nbox; ++p)
+    for (int col = 0; col < q; ++col) {
+      const int b = p * q + col;
+      off[b] = R.hb[p].voff * q + (long long)col * R.hb[p].n;
+      len[b] = R.hb[p].n;
+      nb[b] = multidot_nblocks(len[b]);
+      nbmax = std::max(nbmax, nb[b]);
+      for (int k = 0; k < nb[b]; ++k) ch.push_back(make_int2(b, k));
+    }
+  c->sg_q = 0;
+  HH_TRY(upload(c, &c->d_seg_off, off));
+  HH_TRY(upload(c, &c->d_seg_len, len));
+  HH_TRY(upload(c, &c->d_seg_nb, nb));
+  HH_TRY(upload(c, &c->d_seg_chunk, ch));
+  c->sg.off = c->d_seg_off;
+  c->sg.len = c->d_seg_len;
+  c->sg.nb = c->d_seg_nb;
+  c->sg.chunk = c->d_seg_chunk;
+  c->sg.S = S;
+  c->sg.G = (int)ch.size();
+  c->sg.NBmax = nbmax;
+  c->sg_q = q;
+  return HH_OK;
+}
+
+// Device norms of the outer-loop systems (ensure_segs done): out[b] = ||x_b||_2 on the host.
+hh_status norms(hh_ctx* c, const c128* x, c128* dtmp, std::vector<double>& out) {
+  const int S = c->sg.S;
+  HH_TRY(ensure_partial(c, (size_t)S * c->sg.NBmax));
+  HH_CHECK(launch_multidot(1, c->sg, x, 0, x, c->d_partial, dtmp, c->stream));
+  std::vector<c128> h(S);
+  HH_CHECK(hipMemcpyAsync(h.data(), dtmp, S * sizeof(c128), hipMemcpyDeviceToHost, c->stream));
   HH_TRY(sync(c));
-  out.resize(q);
-  for (int b = 0; b < q; ++b) out[b] = std::sqrt(std::max(h[b].x, 0.0));
+  out.resize(S);
+  for (int b = 0; b < S; ++b) out[b] = std::sqrt(std::max(h[b].x, 0.0));
   return HH_OK;
 }
 
@@ -421,17 +500,29 @@ hh_status hh_release_cached_memory(int64_t* bytes) {
 }
 
 hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_options* o, hh_ctx** out) {
-  if (!A || !d || !out) return HH_EINVAL;
+  return hh_setup_batch(1, A, d, o, out);
+}
+
+hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposition* d, const hh_options* o,
+                         hh_ctx** out) {
+  if (!A || !d || !out || nprob < 1) return HH_EINVAL;
   *out = nullptr;
-  if (A->dim != 1 && A->dim != 2) return HH_EINVAL;
-  if (A->n_cells < 2 || A->n_cells > (1 << 15)) return HH_EINVAL;
-  const long long N1 = A->n_cells + 1;
-  const long long nn = A->dim == 2 ? N1 * N1 : N1;
-  if (A->k) {
-    for (long long i = 0; i < nn; ++i)
-      if (!std::isfinite(A->k[i]) || A->k[i] < 0.0) return HH_EINVAL;
-  } else if (!std::isfinite(A->k_const) || A->k_const < 0.0) {
-    return HH_EINVAL;
+  std::vector<Geometry> parts(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    const hh_operator& Ap = A[p];
+    if (Ap.dim != 1 && Ap.dim != 2) return HH_EINVAL;
+    if (Ap.n_cells < 2 || Ap.n_cells > (1 << 15)) return HH_EINVAL;
+    if (Ap.dim != A[0].dim || d[p].levels != d[0].levels) return HH_EINVAL;
+    const long long N1 = Ap.n_cells + 1;
+    const long long nn = Ap.dim == 2 ? N1 * N1 : N1;
+    if (Ap.k) {
+      for (long long i = 0; i < nn; ++i)
+        if (!std::isfinite(Ap.k[i]) || Ap.k[i] < 0.0) return HH_EINVAL;
+    } else if (!std::isfinite(Ap.k_const) || Ap.k_const < 0.0) {
+      return HH_EINVAL;
+    }
+    if (!build_geometry(Ap.dim, Ap.n_cells, d[p].levels, d[p].m, d[p].overlap_cells, parts[p]).empty())
+      return HH_EINVAL;
   }
   hh_ctx* c = new (std::nothrow) hh_ctx();
   if (!c) return HH_ENOMEM;
@@ -442,30 +533,46 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
     c->restart = o->gmres_restart > 0 ? std::min(o->gmres_restart, 120) : 50;
     c->reorth_eta = o->full_reorth ? 2.0 : 0.125;
   }
-  std::string msg = build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, c->geo);
-  if (!msg.empty()) {
+  if (!merge_geometries(parts, c->geo).empty()) {
     delete c;
     return HH_EINVAL;
   }
+  parts.clear();
+  c->nprob = nprob;
   c->L = d->levels;
+  // inner steps per level: the largest any problem asks for (the batch advances together)
   c->inner.assign(c->L + 1, 1);
-  for (int l = 1; l <= c->L; ++l) c->inner[l] = d->inner_iters[l - 1] > 0 ? d->inner_iters[l - 1] : 1;
+  for (int p = 0; p < nprob; ++p)
+    for (int l = 1; l <= c->L; ++l) c->inner[l] = std::max(c->inner[l], std::max(1, (int)d[p].inner_iters[l - 1]));
   hh_status st = HH_OK;
   auto bail = [&](hh_status s) {
     hh_destroy(c);
     return s;
   };
-  // operator
-  c->op.kc = A->k_const;
-  c->op.h = 1.0 / A->n_cells;
-  c->op.ih2 = (double)A->n_cells * (double)A->n_cells;
-  c->op.N1 = (int)N1;
-  c->op.dim = A->dim;
-  if (A->k) {
-    std::vector<double> kv(A->k, A->k + nn);
-    if ((st = upload(c, &c->d_k, kv)) != HH_OK) return bail(st);
+  // operators: one table row per problem, wavenumbers concatenated
+  std::vector<double> kv;
+  std::vector<long long> koff(nprob, -1);
+  for (int p = 0; p < nprob; ++p) {
+    const hh_operator& Ap = A[p];
+    const long long N1 = Ap.n_cells + 1;
+    const long long nn = Ap.dim == 2 ? N1 * N1 : N1;
+    if (Ap.k) {
+      koff[p] = (long long)kv.size();
+      kv.insert(kv.end(), Ap.k, Ap.k + nn);
+    }
   }
-  c->op.k = c->d_k;
+  if ((st = upload(c, &c->d_k, kv)) != HH_OK) return bail(st);
+  c->hops.resize(nprob);
+  for (int p = 0; p < nprob; ++p) {
+    OpDev& op = c->hops[p];
+    op.kc = A[p].k_const;
+    op.h = 1.0 / A[p].n_cells;
+    op.ih2 = (double)A[p].n_cells * (double)A[p].n_cells;
+    op.N1 = A[p].n_cells + 1;
+    op.dim = A[p].dim;
+    op.k = koff[p] >= 0 ? c->d_k + koff[p] : nullptr;
+  }
+  if ((st = upload(c, &c->d_ops, c->hops)) != HH_OK) return bail(st);
   // levels
   c->lv.resize(c->L + 1);
   for (int l = 0; l <= c->L; ++l) {
@@ -483,6 +590,7 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
       b.op0 = h.op0; b.op1 = h.op1; b.oq0 = h.oq0; b.oq1 = h.oq1;
       b.nx = h.nx(); b.ny = h.ny(); b.n = h.n();
       b.parent = h.parent < 0 ? 0 : h.parent;
+      b.prob = h.prob;
       if (l > 0) {
         const HBox& ph = c->geo.levels[l - 1][h.parent];
         b.pp0 = ph.p0; b.pq0 = ph.q0; b.pny = ph.ny();
@@ -517,6 +625,9 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
   c->g_total = goff;
   for (int l = 0; l <= c->L; ++l)
     if ((st = push_boxes(c, c->lv[l])) != HH_OK) return bail(st);
+  if ((st = group_leaves(c, leaf, leaf_sweep_bucket, leaf.sweep_groups, &leaf.d_sweep_order)) != HH_OK ||
+      (st = group_leaves(c, leaf, leaf_factor_bucket, leaf.factor_groups, &leaf.d_factor_order)) != HH_OK)
+    return bail(st);
   // tail padding (zeroed): the sweeps read whole column slices and row groups past a line's end
   const long long gpad = 256LL * 256LL;
   if ((st = dalloc(c, &c->G, (size_t)(goff + gpad))) != HH_OK) return bail(st);
@@ -524,8 +635,10 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
     return bail(device_fail(c, "fill", hipGetLastError()));
   const int ninfo = 3 * leaf.nbox;
   if ((st = dalloc(c, &c->d_info, (size_t)std::max(ninfo, 4096))) != HH_OK) return bail(st);
-  if (launch_leaf_factor(c->op, leaf.d, leaf.nbox, leaf.max_ny, c->G, c->d_info, c->stream) != hipSuccess)
-    return bail(device_fail(c, "leaf factor", hipGetLastError()));
+  for (const LeafGroup& g : leaf.factor_groups)
+    if (launch_leaf_factor(c->d_ops, leaf.d, leaf.nbox, leaf.d_factor_order + g.start, g.count, g.max_ny, c->G,
+                           c->d_info, c->stream) != hipSuccess)
+      return bail(device_fail(c, "leaf factor", hipGetLastError()));
   std::vector<int> info(ninfo);
   if (hipMemcpyAsync(info.data(), c->d_info, ninfo * sizeof(int), hipMemcpyDeviceToHost, c->stream) !=
           hipSuccess ||
@@ -565,6 +678,17 @@ hh_status hh_level_info(const hh_ctx* cc, int32_t level, int32_t rank, int32_t o
     if (m_in) m_in[i] = mi;
     if (r) r[i] = (int32_t)rr;
     if (s) s[i] = (int32_t)ss;
+  }
+  return HH_OK;
+}
+
+hh_status hh_problem_layout(const hh_ctx* c, int32_t* nprob, int64_t* n_nodes, int64_t* offset) {
+  if (!c) return HH_EINVAL;
+  const Level& R = c->lv[0];
+  if (nprob) *nprob = R.nbox;
+  for (int p = 0; p < R.nbox; ++p) {
+    if (n_nodes) n_nodes[p] = R.hb[p].n;
+    if (offset) offset[p] = R.hb[p].voff;
   }
   return HH_OK;
 }
@@ -800,11 +924,11 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   BC(launch_iface_scatter(Lv.d, Lv.nbox, q, Lv.d_if, d_omoff, Om, 0, Lv.R, s));
   BT(solve_level(c, level, q, Lv.R, Lv.X));
   // Y = stacked traces on the neighbours; Q = qr(Y)
-  BC(launch_trace(c->op, Lv.d, Lv.nbox, q, Lv.d_rows, d_yoff, Lv.X, Y, s));
+  BC(launch_trace(c->d_ops, Lv.d, Lv.nbox, q, Lv.d_rows, d_yoff, Lv.X, Y, s));
   BC(launch_qr(Lv.nbox, d_qm, d_qn, d_yoff, Y, d_soff, Rs, Wk, s));
   // B^H = B_i conj(S_i(conj((B_i^o)^H Q)))
   BC(launch_fill_zero(Lv.R, nlev * sizeof(c128), s));
-  BC(launch_trace_adjoint(c->op, Lv.d, Lv.nbox, q, Lv.d_rows, Lv.d_seg_ptr, Lv.d_seg_y, Lv.d_adj, d_yoff, Y, Lv.R,
+  BC(launch_trace_adjoint(c->d_ops, Lv.d, Lv.nbox, q, Lv.d_rows, Lv.d_seg_ptr, Lv.d_seg_y, Lv.d_adj, d_yoff, Y, Lv.R,
                           s));
   BC(launch_conj_inplace(Lv.R, nlev, s));
   BT(solve_level(c, level, q, Lv.R, Lv.X));
@@ -820,7 +944,7 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   BT(solve_level(c, level, rmax, Lv.R, Lv.X));
   BC(launch_extract_owned(Lv.d, Lv.nbox, Lv.max_own, rmax, Lv.X, Lv.C, s));
   // A_c = C^H A_P C, then its inverse
-  BC(launch_galerkin_ac(c->op, Lv.d, Lv.nbox, P.d, Lv.d_dil, max_dil, rmax, Lv.C, Lv.AC, s));
+  BC(launch_galerkin_ac(c->d_ops, Lv.d, Lv.nbox, P.d, Lv.d_dil, max_dil, rmax, Lv.C, Lv.AC, s));
   BC(launch_fill_zero(P.Ainv, nc2 * sizeof(c128), s));
   BC(launch_galerkin_blocks(Lv.d, P.dp, Lv.d_pairs, Lv.npairs, rmax, Lv.d_dil, Lv.C, Lv.AC, P.Ainv, s));
   BC(launch_copy(P.Ainv, P.Araw, nc2, s));
@@ -843,7 +967,7 @@ hh_status hh_apply_operator(hh_ctx* c, int32_t nrhs, const void* x, const void* 
   HH_TRY(check_usable(c));
   if (nrhs <= 0 || !x || !y || (mode == 1 && !b) || (mode != 0 && mode != 1)) return fail(c, HH_EINVAL, "bad args");
   Level& R = c->lv[0];
-  HH_CHECK(launch_apply_box(c->op, R.d, 1, R.max_n, nrhs, reinterpret_cast<const c128*>(x),
+  HH_CHECK(launch_apply_box(c->d_ops, R.d, R.nbox, R.max_n, nrhs, reinterpret_cast<const c128*>(x),
                             reinterpret_cast<const c128*>(b), reinterpret_cast<c128*>(y), mode, c->stream));
   return sync(c);
 }
@@ -861,9 +985,13 @@ hh_status hh_precondition(hh_ctx* c, int32_t nrhs, const void* r, void* z) {
 
 namespace {
 
+// Right-preconditioned restarted GMRES (flexible form: Z_j = B v_j kept) for
+// every outer-loop system at once; q right-hand sides per problem, S systems.
 hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit, const std::vector<double>& nb,
                 std::vector<int>& iters, std::vector<double>& relres, std::vector<int>& conv) {
   const long long n = c->lv[0].total;
+  const SegDev& sg = c->sg;
+  const int S = sg.S;
   const int m = std::max(1, std::min(c->restart, std::max(maxit, 1)));
   hipStream_t s = c->stream;
   c128 *Vb = nullptr, *Zb = nullptr, *W = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
@@ -880,21 +1008,21 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     if ((st = dalloc(c, &Vb, (size_t)(m + 1) * q * n)) != HH_OK) break;
     if ((st = dalloc(c, &Zb, (size_t)m * q * n)) != HH_OK) break;
     if ((st = dalloc(c, &W, (size_t)q * n)) != HH_OK) break;
-    if ((st = dalloc(c, &H, (size_t)q * (m + 1) * m)) != HH_OK) break;
-    if ((st = dalloc(c, &cs, (size_t)q * m)) != HH_OK) break;
-    if ((st = dalloc(c, &sn, (size_t)q * m)) != HH_OK) break;
-    if ((st = dalloc(c, &g, (size_t)q * (m + 1))) != HH_OK) break;
-    if ((st = dalloc(c, &h1, (size_t)q * (m + 2))) != HH_OK) break;
-    if ((st = dalloc(c, &need, (size_t)q)) != HH_OK) break;
-    if ((st = dalloc(c, &h2, (size_t)q * (m + 1))) != HH_OK) break;
-    if ((st = dalloc(c, &tmp, (size_t)q * (m + 1))) != HH_OK) break;
-    if ((st = dalloc(c, &y, (size_t)q * m)) != HH_OK) break;
-    if ((st = dalloc(c, &hn, (size_t)q)) != HH_OK) break;
-    if ((st = dalloc(c, &est, (size_t)q)) != HH_OK) break;
-    if ((st = dalloc(c, &thr, (size_t)q)) != HH_OK) break;
-    if ((st = dalloc(c, &state, (size_t)3 * q)) != HH_OK) break;
+    if ((st = dalloc(c, &H, (size_t)S * (m + 1) * m)) != HH_OK) break;
+    if ((st = dalloc(c, &cs, (size_t)S * m)) != HH_OK) break;
+    if ((st = dalloc(c, &sn, (size_t)S * m)) != HH_OK) break;
+    if ((st = dalloc(c, &g, (size_t)S * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &h1, (size_t)S * (m + 2))) != HH_OK) break;
+    if ((st = dalloc(c, &need, (size_t)S)) != HH_OK) break;
+    if ((st = dalloc(c, &h2, (size_t)S * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &tmp, (size_t)S * (m + 1))) != HH_OK) break;
+    if ((st = dalloc(c, &y, (size_t)S * m)) != HH_OK) break;
+    if ((st = dalloc(c, &hn, (size_t)S)) != HH_OK) break;
+    if ((st = dalloc(c, &est, (size_t)S)) != HH_OK) break;
+    if ((st = dalloc(c, &thr, (size_t)S)) != HH_OK) break;
+    if ((st = dalloc(c, &state, (size_t)3 * S)) != HH_OK) break;
     if ((st = dalloc(c, &any, (size_t)2)) != HH_OK) break;
-    if ((st = ensure_partial(c, (size_t)(m + 2) * q * multidot_nblocks(n))) != HH_OK) break;
+    if ((st = ensure_partial(c, (size_t)(m + 2) * S * sg.NBmax)) != HH_OK) break;
     if ((st = ensure_poll(c)) != HH_OK) break;
   } while (false);
   if (st != HH_OK) {
@@ -918,54 +1046,54 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     }                         \
   } while (0)
   const long long vs = (long long)q * n;
-  std::vector<double> beta(q), th(q);
-  std::vector<int> hstate(3 * q);
-  for (int k = 0; k < q; ++k) th[k] = rtol * nb[k];
-  GC(hipMemcpyAsync(thr, th.data(), q * sizeof(double), hipMemcpyHostToDevice, s));
+  std::vector<double> beta(S), th(S);
+  std::vector<int> hstate(3 * S);
+  for (int k = 0; k < S; ++k) th[k] = rtol * nb[k];
+  GC(hipMemcpyAsync(thr, th.data(), S * sizeof(double), hipMemcpyHostToDevice, s));
   // u = 0, r = b
   GC(launch_fill_zero(u, vs * (long long)sizeof(c128), s));
   GC(launch_copy(b, W, vs, s));
-  GT(norms(c, q, n, W, tmp, beta));
+  GT(norms(c, W, tmp, beta));
   int* poll = c->poll;
   while (true) {
     bool any_active = false;
-    for (int k = 0; k < q; ++k) {
+    for (int k = 0; k < S; ++k) {
       relres[k] = nb[k] > 0.0 ? beta[k] / nb[k] : 0.0;
       conv[k] = relres[k] < rtol || nb[k] == 0.0;
       hstate[k] = !conv[k] && iters[k] < maxit;
-      hstate[q + k] = 0;
-      hstate[2 * q + k] = iters[k];
+      hstate[S + k] = 0;
+      hstate[2 * S + k] = iters[k];
       any_active = any_active || hstate[k];
     }
     if (!any_active) break;
     // V_0 = r / beta (tmp holds ||r||^2 from norms()); g = beta e_1
-    GC(launch_normalize(q, n, tmp, W, Vb, nullptr, s));
-    std::vector<c128> g0((size_t)q * (m + 1), make_double2(0.0, 0.0));
-    for (int k = 0; k < q; ++k) g0[(size_t)k * (m + 1)] = make_double2(beta[k], 0.0);
+    GC(launch_normalize(sg, tmp, W, Vb, nullptr, s));
+    std::vector<c128> g0((size_t)S * (m + 1), make_double2(0.0, 0.0));
+    for (int k = 0; k < S; ++k) g0[(size_t)k * (m + 1)] = make_double2(beta[k], 0.0);
     GC(hipMemcpyAsync(g, g0.data(), g0.size() * sizeof(c128), hipMemcpyHostToDevice, s));
-    GC(hipMemcpyAsync(state, hstate.data(), 3 * q * sizeof(int), hipMemcpyHostToDevice, s));
+    GC(hipMemcpyAsync(state, hstate.data(), 3 * S * sizeof(int), hipMemcpyHostToDevice, s));
     for (int j = 0; j < m; ++j) {
       const c128* vj = Vb + j * vs;
       c128* zj = Zb + j * vs;
       GT(two_level(c, 0, q, vj, zj));
-      GC(launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, zj, nullptr, W, 0, s));
+      GC(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, zj, nullptr, W, 0, s));
       // classical Gram-Schmidt twice; the second update also gives ||w||^2
       // classical Gram-Schmidt; the second pass runs for the columns whose first
       // pass cancelled by more than the factor reorth_eta (all columns when >= 1)
       const double vbytes = 16.0 * (double)n * q;
       {
         ProfScope ps(c, 2, vbytes * (j + 1 + (j + 8) / 8), 8.0 * n * q * (j + 1));
-        GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h1, s, 1));
+        GC(launch_multidot(j + 1, sg, Vb, vs, W, c->d_partial, h1, s, 1));
       }
       {
         ProfScope ps(c, 1, vbytes * (j + 3), 8.0 * n * q * (j + 1));
-        GC(launch_basis_update(j + 1, q, n, Vb, vs, h1, W, c->d_partial, tmp, s));
+        GC(launch_basis_update(j + 1, sg, Vb, vs, h1, W, c->d_partial, tmp, s));
       }
-      GC(launch_reorth_flag(q, j + 1, h1 + (size_t)(j + 1) * q, tmp, c->reorth_eta, need, h2, s));
-      GC(launch_multidot(j + 1, q, n, Vb, vs, W, c->d_partial, h2, s, 0, need));
-      GC(launch_basis_update(j + 1, q, n, Vb, vs, h2, W, c->d_partial, tmp, s, need));
-      GC(launch_normalize(q, n, tmp, W, Vb + (j + 1) * vs, hn, s));
-      GC(launch_gmres_step(q, j, m, H, h1, h2, hn, cs, sn, g, est, state, thr, maxit, any, s));
+      GC(launch_reorth_flag(S, j + 1, h1 + (size_t)(j + 1) * S, tmp, c->reorth_eta, need, h2, s));
+      GC(launch_multidot(j + 1, sg, Vb, vs, W, c->d_partial, h2, s, 0, need));
+      GC(launch_basis_update(j + 1, sg, Vb, vs, h2, W, c->d_partial, tmp, s, need));
+      GC(launch_normalize(sg, tmp, W, Vb + (j + 1) * vs, hn, s));
+      GC(launch_gmres_step(S, j, m, H, h1, h2, hn, cs, sn, g, est, state, thr, maxit, any, s));
       // poll the active count one step late so the stream never drains
       GC(hipMemcpyAsync(poll + (j & 1), any, sizeof(int), hipMemcpyDeviceToHost, s));
       GC(hipEventRecord(c->poll_ev[j & 1], s));
@@ -974,13 +1102,13 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
         if (poll[(j - 1) & 1] == 0) break;
       }
     }
-    GC(hipMemcpyAsync(hstate.data(), state, 3 * q * sizeof(int), hipMemcpyDeviceToHost, s));
+    GC(hipMemcpyAsync(hstate.data(), state, 3 * S * sizeof(int), hipMemcpyDeviceToHost, s));
     GC(hipStreamSynchronize(s));
-    for (int k = 0; k < q; ++k) iters[k] = hstate[2 * q + k];
-    GC(launch_gmres_solve_small(q, m, state + q, H, g, y, s));
-    GC(launch_basis_combine(q, n, state + q, Zb, vs, y, u, s));
-    GC(launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, u, b, W, 1, s));
-    GT(norms(c, q, n, W, tmp, beta));
+    for (int k = 0; k < S; ++k) iters[k] = hstate[2 * S + k];
+    GC(launch_gmres_solve_small(S, m, state + S, H, g, y, s));
+    GC(launch_basis_combine(sg, state + S, Zb, vs, y, u, s));
+    GC(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, u, b, W, 1, s));
+    GT(norms(c, W, tmp, beta));
   }
   cleanup();
 #undef GC
@@ -992,6 +1120,7 @@ hh_status stationary(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int 
                      std::vector<int>& iters, std::vector<double>& relres, std::vector<int>& conv) {
   const long long n = c->lv[0].total;
   const long long vs = (long long)q * n;
+  const int S = c->sg.S;
   hipStream_t s = c->stream;
   c128 *r = nullptr, *z = nullptr, *tmp = nullptr;
   int* act = nullptr;
@@ -1000,12 +1129,12 @@ hh_status stationary(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int 
     for (void* p : std::initializer_list<void*>{r, z, tmp, act}) dfree(c, p);
   };
   if ((st = dalloc(c, &r, (size_t)vs)) != HH_OK || (st = dalloc(c, &z, (size_t)vs)) != HH_OK ||
-      (st = dalloc(c, &tmp, (size_t)q)) != HH_OK || (st = dalloc(c, &act, (size_t)q)) != HH_OK) {
+      (st = dalloc(c, &tmp, (size_t)S)) != HH_OK || (st = dalloc(c, &act, (size_t)S)) != HH_OK) {
     cleanup();
     return st;
   }
-  std::vector<double> rn(q);
-  std::vector<int> active(q);
+  std::vector<double> rn(S);
+  std::vector<int> active(S);
   hipError_t e;
   if ((e = launch_fill_zero(u, vs * (long long)sizeof(c128), s)) != hipSuccess ||
       (e = launch_copy(b, r, vs, s)) != hipSuccess) {
@@ -1013,9 +1142,9 @@ hh_status stationary(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int 
     return device_fail(c, "stationary init", e);
   }
   while (true) {
-    if ((st = norms(c, q, n, r, tmp, rn)) != HH_OK) break;
+    if ((st = norms(c, r, tmp, rn)) != HH_OK) break;
     bool any = false;
-    for (int k = 0; k < q; ++k) {
+    for (int k = 0; k < S; ++k) {
       relres[k] = nb[k] > 0.0 ? rn[k] / nb[k] : 0.0;
       conv[k] = relres[k] < rtol || nb[k] == 0.0;
       active[k] = !conv[k] && iters[k] < maxit;
@@ -1023,13 +1152,13 @@ hh_status stationary(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int 
     }
     if (!any) break;
     if ((st = two_level(c, 0, q, r, z)) != HH_OK) break;
-    if ((e = hipMemcpyAsync(act, active.data(), q * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = launch_add_masked(z, u, n, q, act, s)) != hipSuccess ||
-        (e = launch_apply_box(c->op, c->lv[0].d, 1, c->lv[0].max_n, q, u, b, r, 1, s)) != hipSuccess) {
+    if ((e = hipMemcpyAsync(act, active.data(), S * sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = launch_seg_add(c->sg, act, z, u, s)) != hipSuccess ||
+        (e = launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, u, b, r, 1, s)) != hipSuccess) {
       cleanup();
       return device_fail(c, "stationary step", e);
     }
-    for (int k = 0; k < q; ++k) iters[k] += active[k];
+    for (int k = 0; k < S; ++k) iters[k] += active[k];
   }
   cleanup();
   return st;
@@ -1043,26 +1172,26 @@ extern "C" hh_status hh_solve(hh_ctx* c, int32_t nrhs, const void* f, const void
   if (nrhs <= 0 || !f || !u || maxit < 0 || !(rtol >= 0.0)) return fail(c, HH_EINVAL, "bad arguments to hh_solve");
   HH_TRY(check_built(c));
   const int q = nrhs;
-  const long long n = c->lv[0].total;
   HH_TRY(ensure_work(c, 0, q));
+  HH_TRY(ensure_segs(c, q));
+  const int S = c->sg.S;
   Level& R0 = c->lv[0];
   const c128* b = reinterpret_cast<const c128*>(f);
   if (g) {
     // b = f + (boundary facets)/2^(dim-1) * g / h, built by the stencil kernel's rhs mode on E
-    HH_CHECK(launch_rhs_with_impedance(c->op, R0.d, q, b, reinterpret_cast<const c128*>(g), R0.E, c->stream));
+    HH_CHECK(launch_rhs_with_impedance(c->d_ops, R0.d, R0.nbox, q, b, reinterpret_cast<const c128*>(g), R0.E, c->stream));
     b = R0.E;
   }
   std::vector<double> nb;
-  HH_TRY(ensure_partial(c, (size_t)q * multidot_nblocks(n)));
   c128* tmp = nullptr;
-  HH_TRY(dalloc(c, &tmp, (size_t)q));
-  hh_status st = norms(c, q, n, b, tmp, nb);
+  HH_TRY(dalloc(c, &tmp, (size_t)S));
+  hh_status st = norms(c, b, tmp, nb);
   dfree(c, tmp);
   if (st != HH_OK) return st;
   for (double v : nb)
     if (!std::isfinite(v)) return fail(c, HH_EINVAL, "right-hand side holds NaN or Inf");
-  std::vector<int> iters(q, 0), conv(q, 0);
-  std::vector<double> relres(q, 0.0);
+  std::vector<int> iters(S, 0), conv(S, 0);
+  std::vector<double> relres(S, 0.0);
   if (c->outer == HH_GMRES)
     st = gmres(c, q, b, reinterpret_cast<c128*>(u), rtol, maxit, nb, iters, relres, conv);
   else
@@ -1073,7 +1202,7 @@ extern "C" hh_status hh_solve(hh_ctx* c, int32_t nrhs, const void* f, const void
     prof_collect(c);
   }
   bool all = true;
-  for (int k = 0; k < q; ++k) {
+  for (int k = 0; k < S; ++k) {
     if (info) {
       info[k].iters = iters[k];
       info[k].converged = conv[k];

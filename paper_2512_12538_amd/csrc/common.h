@@ -91,7 +91,7 @@ struct BoxDev {
   int own_ny;             // owned width in q
   int tr_off, tr_cnt;     // trace rows of the interface map of this box
   int adj_off, adj_cnt;   // adjoint-trace entries (CSR over owned nodes)
-  int pad0;
+  int prob;               // problem of the box (row of the operator table)
   long long voff;         // node offset of this box in a level buffer
   long long goff;         // offset (in complex entries) of this box's block factors
   long long coff;         // offset (in complex entries) of this box's coarse block C_i

@@ -91,6 +91,32 @@ std::string build_geometry(int dim, int n_cells, int levels, const int (*m)[2], 
   return "";
 }
 
+std::string merge_geometries(const std::vector<Geometry>& parts, Geometry& g) {
+  if (parts.empty()) return "no problems";
+  const int depth = parts[0].depth();
+  g = Geometry();
+  g.dim = parts[0].dim;
+  g.n_cells = parts[0].n_cells;
+  g.levels.assign(depth + 1, {});
+  std::vector<int> base(depth + 1, 0);
+  for (size_t p = 0; p < parts.size(); ++p) {
+    const Geometry& h = parts[p];
+    if (h.dim != g.dim || h.depth() != depth) return "problems of a batch need the same dimension and depth";
+    for (int l = 0; l <= depth; ++l) {
+      for (HBox b : h.levels[l]) {
+        b.prob = (int)p;
+        b.index += base[l];
+        if (b.parent >= 0) b.parent += base[l - 1];
+        for (int& c : b.children) c += base[l + 1];
+        for (int& o : b.nbrs) o += base[l];
+        g.levels[l].push_back(std::move(b));
+      }
+    }
+    for (int l = 0; l <= depth; ++l) base[l] += (int)h.levels[l].size();
+  }
+  return "";
+}
+
 void trace_tables(const Geometry& g, int level, int i, std::vector<TraceRow>& rows,
                   std::vector<AdjEntry>& adj) {
   rows.clear();

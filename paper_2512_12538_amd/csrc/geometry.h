@@ -9,6 +9,7 @@
 
 struct HBox {
   int level = 0, index = 0, parent = -1;
+  int prob = 0;              // problem of a merged batch (merge_geometries)
   int a = 0, b = 0;          // position among the parent's children (x slow, y fast)
   int I = 0, J = 0;          // position among all boxes of the level
   int dx0 = 0, dx1 = 0, dy0 = 0, dy1 = 0;  // non-overlapping (element-based) box, in cells
@@ -37,6 +38,12 @@ struct Geometry {
 // in cells (even).  Returns an empty string on success or a message.
 std::string build_geometry(int dim, int n_cells, int levels, const int (*m)[2], const int* overlap,
                            Geometry& g);
+
+// Concatenates the hierarchies of independent problems (same dim and depth)
+// level by level: problem p's boxes follow those of problems < p, with every
+// box index (parent, children, neighbours) shifted and prob = p.  Returns an
+// empty string on success or a message.
+std::string merge_geometries(const std::vector<Geometry>& parts, Geometry& g);
 
 // Rows of the interface map of box i at level l: (neighbour j, local node of j)
 // for every interface node of every neighbour whose stencil row touches a node

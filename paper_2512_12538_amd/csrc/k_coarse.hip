@@ -22,11 +22,12 @@ __device__ __forceinline__ bool owns(const BoxDev& B, int p, int q) {
 }
 
 // AC[box][b][x] = (A_P C_box[b])(x) for x in the dilated owned box dil = (p0, p1, q0, q1)
-__global__ void __launch_bounds__(TB) k_galerkin_ac(OpDev op, const BoxDev* __restrict__ boxes,
+__global__ void __launch_bounds__(TB) k_galerkin_ac(const OpDev* __restrict__ ops, const BoxDev* __restrict__ boxes,
                                                     const BoxDev* __restrict__ par, const int4* __restrict__ dil,
                                                     int rmax, const c128* __restrict__ C, c128* __restrict__ AC) {
   const int box = blockIdx.y / rmax, col = blockIdx.y % rmax;
   const BoxDev B = boxes[box];
+  const OpDev op = ops[B.prob];
   if (col >= B.r) return;
   const BoxDev P = par[B.parent];
   const int4 d = dil[box];
@@ -396,10 +397,10 @@ inline int gx(long long n, int cap) {
 
 }  // namespace
 
-hipError_t launch_galerkin_ac(const OpDev& op, const BoxDev* boxes, int nbox, const BoxDev* par, const int4* dil,
+hipError_t launch_galerkin_ac(const OpDev* ops, const BoxDev* boxes, int nbox, const BoxDev* par, const int4* dil,
                               int max_dil, int rmax, const c128* C, c128* AC, hipStream_t s) {
   if (nbox <= 0 || rmax <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_galerkin_ac, dim3(gx(max_dil, 256), nbox * rmax), dim3(TB), 0, s, op, boxes, par, dil, rmax,
+  hipLaunchKernelGGL(k_galerkin_ac, dim3(gx(max_dil, 256), nbox * rmax), dim3(TB), 0, s, ops, boxes, par, dil, rmax,
                      C, AC);
   return hipGetLastError();
 }

@@ -128,28 +128,49 @@ __device__ __forceinline__ double block_sum1(double v, double* red) {
   return r;
 }
 
-// partial[blk*S + k*q + b] = sum over the block's chunk of conj(V_k[b]) W[b],
+// Chunk g of the outer-loop systems: system b, its elements [lo, hi) relative
+// to the segment start (nb[b] chunks of equal length per system, the last one
+// shorter), so the split depends on the system's length only.
+struct Chunk {
+  int b, blk;
+  long long off, lo, hi;
+};
+__device__ __forceinline__ Chunk chunk_of(const SegDev& sg, int g) {
+  const int2 cb = sg.chunk[g];
+  Chunk c;
+  c.b = cb.x;
+  c.blk = cb.y;
+  const long long len = sg.len[c.b];
+  const int nbk = sg.nb[c.b];
+  const long long per = (len + nbk - 1) / nbk;
+  c.off = sg.off[c.b];
+  c.lo = c.blk * per;
+  c.hi = c.lo + per < len ? c.lo + per : len;
+  return c;
+}
+
+// partial[blk*S1 + k*S + b] = sum over chunk blk of system b of conj(V_k[b]) W[b],
 // KG consecutive k per block so that W is read once per KG products; each
 // thread keeps KG x EPT basis loads in flight.  With wnorm, the first group
-// also accumulates |W[b]|^2 into row nk.  Columns with skip[b] == 0 are left
-// untouched (skip may be null).  S = (nk + wnorm) * q: the final sums read
-// consecutive entries per block.  One-dimensional XCD-aware grid: logical
-// block ((b * NB + blk) * NKG + kg), contiguous per XCD, so the groups that
-// share a chunk of W run on one XCD and read it from its L2.
-__global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, int NB, int S, const c128* __restrict__ V,
+// also accumulates |W[b]|^2 into row nk.  Systems with skip[b] == 0 are left
+// untouched (skip may be null).  S1 = (nk + wnorm) * S: the final sums read
+// consecutive entries per chunk index.  One-dimensional XCD-aware grid:
+// logical block (g * NKG + kg), contiguous per XCD, so the groups that share a
+// chunk of W run on one XCD and read it from its L2.
+__global__ void __launch_bounds__(TB) k_dot_partial(int nk, SegDev sg, int S1, const c128* __restrict__ V,
                                                     long long vstride, const c128* __restrict__ W,
                                                     c128* __restrict__ partial, int wnorm,
                                                     const int* __restrict__ skip) {
   const int nkg = (nk + KG - 1) / KG;
   const int lb = (blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
-  if (lb >= NB * nkg * q) return;
-  const int kg = lb % nkg, t = lb / nkg;
-  const int blk = t % NB, k0 = kg * KG, b = t / NB;
+  if (lb >= sg.G * nkg) return;
+  const int kg = lb % nkg;
+  const Chunk ch = chunk_of(sg, lb / nkg);
+  const int b = ch.b, blk = ch.blk, k0 = kg * KG;
   if (skip && !skip[b]) return;
-  const long long per = (n + NB - 1) / NB;
-  const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
-  const c128* w = W + (long long)b * n;
-  const c128* vb = V + (long long)b * n;
+  const long long lo = ch.lo, hi = ch.hi;
+  const c128* w = W + ch.off;
+  const c128* vb = V + ch.off;
   const bool wn = wnorm && k0 == 0;
   const int kn = nk - k0 < KG ? nk - k0 : KG;
   double2 acc[KG];
@@ -182,37 +203,41 @@ __global__ void __launch_bounds__(TB) k_dot_partial(int nk, int q, long long n, 
   }
   __shared__ double2 red[(TB / 64) * KG];
   const double2 r = block_sum8(acc, red);
-  if (threadIdx.x < kn) partial[(long long)blk * S + (k0 + threadIdx.x) * q + b] = r;
+  const int S = sg.S;
+  if (threadIdx.x < kn) partial[(long long)blk * S1 + (k0 + threadIdx.x) * S + b] = r;
   if (wn) {
     const double rn = block_sum1(nw, reinterpret_cast<double*>(red));
-    if (threadIdx.x == 0) partial[(long long)blk * S + nk * q + b] = mk(rn, 0.0);
+    if (threadIdx.x == 0) partial[(long long)blk * S1 + nk * S + b] = mk(rn, 0.0);
   }
 }
 
-__global__ void k_dot_final(int nkq, int q, int NB, const c128* __restrict__ partial, c128* __restrict__ out,
-                            const int* __restrict__ skip) {
+// out[t] = sum over the chunks of system t % S of partial[blk*nkq + t], in chunk order
+__global__ void k_dot_final(int nkq, int S, const int* __restrict__ nb, const c128* __restrict__ partial,
+                            c128* __restrict__ out, const int* __restrict__ skip) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nkq) return;
-  if (skip && !skip[t % q]) return;
+  const int b = t % S;
+  if (skip && !skip[b]) return;
+  const int NB = nb[b];
   double2 acc = mk(0.0, 0.0);
   for (int blk = 0; blk < NB; ++blk) acc = cadd(acc, partial[(long long)blk * nkq + t]);
   out[t] = acc;
 }
 
-// W[b] -= sum_k V_k[b] h[k*q + b]; optionally the block partial sums of |W[b]|^2
-// after the update (same chunking as the inner products).  The coefficients
-// are uniform per work-group (scalar loads); eight basis vectors x EPT
-// elements are loaded per thread before they are applied.
-__global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n, int NB, const c128* __restrict__ V,
+// W[b] -= sum_k V_k[b] h[k*S + b] over one chunk per work-group; optionally the
+// chunk sums of |W[b]|^2 after the update (npart[blk*S + b]).  The
+// coefficients are uniform per work-group (scalar loads); eight basis vectors
+// x EPT elements are loaded per thread before they are applied.
+__global__ void __launch_bounds__(TB) k_basis_update(int nk, SegDev sg, const c128* __restrict__ V,
                                                      long long vstride, const c128* __restrict__ h,
                                                      c128* __restrict__ W, c128* __restrict__ npart,
                                                      const int* __restrict__ skip) {
-  const int blk = blockIdx.x, b = blockIdx.y;
+  const Chunk ch = chunk_of(sg, blockIdx.x);
+  const int b = ch.b, blk = ch.blk, S = sg.S;
   if (skip && !skip[b]) return;
-  const long long per = (n + NB - 1) / NB;
-  const long long lo = blk * per, hi = lo + per < n ? lo + per : n;
-  const c128* vb = V + (long long)b * n;
-  c128* wb = W + (long long)b * n;
+  const long long lo = ch.lo, hi = ch.hi;
+  const c128* vb = V + ch.off;
+  c128* wb = W + ch.off;
   double nrm = 0.0;
   for (long long i0 = lo; i0 < hi; i0 += CHUNK) {
     double2 w[EPT];
@@ -233,13 +258,13 @@ __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n,
         }
 #pragma unroll
       for (int t = 0; t < KG; ++t) {
-        const double2 hk = h[(k + t) * q + b];
+        const double2 hk = h[(k + t) * S + b];
 #pragma unroll
         for (int e = 0; e < EPT; ++e) w[e] = csub(w[e], cmul(vv[t][e], hk));
       }
     }
     for (; k < nk; ++k) {
-      const double2 hk = h[k * q + b];
+      const double2 hk = h[k * S + b];
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const long long i = i0 + threadIdx.x + (long long)e * TB;
@@ -259,7 +284,7 @@ __global__ void __launch_bounds__(TB) k_basis_update(int nk, int q, long long n,
   if (npart) {
     __shared__ double red[TB / 64];
     const double r = block_sum1(nrm, red);
-    if (threadIdx.x == 0) npart[(long long)blk * q + b] = mk(r, 0.0);
+    if (threadIdx.x == 0) npart[(long long)blk * S + b] = mk(r, 0.0);
   }
 }
 
@@ -276,15 +301,14 @@ __global__ void k_reorth_flag(int q, int nk, const c128* __restrict__ w0n2, cons
     for (int k = 0; k < nk; ++k) h2[k * q + b] = mk(0.0, 0.0);
 }
 
-__global__ void __launch_bounds__(TB) k_normalize(int q, long long n, const c128* __restrict__ nrm2,
+__global__ void __launch_bounds__(TB) k_normalize(SegDev sg, const c128* __restrict__ nrm2,
                                                   const c128* __restrict__ x, c128* __restrict__ y,
                                                   double* __restrict__ nrm) {
-  const int b = blockIdx.y;
-  const double nv = sqrt(fmax(nrm2[b].x, 0.0));
+  const Chunk ch = chunk_of(sg, blockIdx.x);
+  const double nv = sqrt(fmax(nrm2[ch.b].x, 0.0));
   const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0 && nrm) nrm[b] = nv;
-  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB)
-    y[(long long)b * n + i] = cscale(x[(long long)b * n + i], inv);
+  if (ch.blk == 0 && threadIdx.x == 0 && nrm) nrm[ch.b] = nv;
+  for (long long i = ch.lo + threadIdx.x; i < ch.hi; i += TB) y[ch.off + i] = cscale(x[ch.off + i], inv);
 }
 
 // One Arnoldi column per right-hand side: H[:, j] = h1 + h2, H[j+1, j] = ||w||,
@@ -390,49 +414,54 @@ __global__ void k_gmres_solve_small(int q, int m, const int* __restrict__ jdone,
 }
 
 // u[b] += sum_{k < jdone[b]} Z_k[b] y[k][b]
-__global__ void __launch_bounds__(TB) k_basis_combine(int q, long long n, const int* __restrict__ jdone,
+__global__ void __launch_bounds__(TB) k_basis_combine(SegDev sg, const int* __restrict__ jdone,
                                                       const c128* __restrict__ Z, long long zstride,
                                                       const c128* __restrict__ y, c128* __restrict__ u) {
-  const int b = blockIdx.y;
+  const Chunk ch = chunk_of(sg, blockIdx.x);
+  const int b = ch.b, S = sg.S;
   const int jd = jdone[b];
   if (jd == 0) return;
-  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) {
-    double2 acc = u[(long long)b * n + i];
-    for (int k = 0; k < jd; ++k) acc = cfma(Z[k * zstride + (long long)b * n + i], y[k * q + b], acc);
-    u[(long long)b * n + i] = acc;
+  for (long long i = ch.off + ch.lo + threadIdx.x; i < ch.off + ch.hi; i += TB) {
+    double2 acc = u[i];
+    for (int k = 0; k < jd; ++k) acc = cfma(Z[k * zstride + i], y[k * S + b], acc);
+    u[i] = acc;
   }
 }
 
-inline int gx(long long n, int cap) {
-  long long g = (n + TB - 1) / TB;
-  return (int)(g < 1 ? 1 : (g > cap ? cap : g));
+// y[b] += x[b] for the systems with active[b] (active may be null)
+__global__ void __launch_bounds__(TB) k_seg_add(SegDev sg, const int* __restrict__ active,
+                                                const c128* __restrict__ x, c128* __restrict__ y) {
+  const Chunk ch = chunk_of(sg, blockIdx.x);
+  if (active && !active[ch.b]) return;
+  for (long long i = ch.off + ch.lo + threadIdx.x; i < ch.off + ch.hi; i += TB) y[i] = cadd(y[i], x[i]);
 }
+
 
 }  // namespace
 
 int multidot_nblocks(long long n) { return nblocks(n); }
 
-hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long vstride, const c128* W,
+hipError_t launch_multidot(int nk, const SegDev& sg, const c128* V, long long vstride, const c128* W,
                            c128* partial, c128* out, hipStream_t s, int wnorm, const int* skip) {
-  if (nk <= 0 || q <= 0) return hipSuccess;
-  const int NB = nblocks(n);
-  const int nkq = (nk + (wnorm ? 1 : 0)) * q;
-  const long long nlog = (long long)NB * ((nk + KG - 1) / KG) * q;
+  if (nk <= 0 || sg.S <= 0) return hipSuccess;
+  const int nkq = (nk + (wnorm ? 1 : 0)) * sg.S;
+  const long long nlog = (long long)sg.G * ((nk + KG - 1) / KG);
   if (nlog > (1LL << 30)) return hipErrorInvalidValue;
   const long long grid = (nlog + NXCD - 1) / NXCD * NXCD;
-  hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)grid), dim3(TB), 0, s, nk, q, n, NB, nkq, V, vstride, W, partial,
-                     wnorm, skip);
-  hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, q, NB, partial, out, skip);
+  hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)grid), dim3(TB), 0, s, nk, sg, nkq, V, vstride, W, partial, wnorm,
+                     skip);
+  hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, sg.S, sg.nb, partial, out, skip);
   return hipGetLastError();
 }
 
-hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h, c128* W,
+hipError_t launch_basis_update(int nk, const SegDev& sg, const c128* V, long long vstride, const c128* h, c128* W,
                                c128* partial, c128* nrm2, hipStream_t s, const int* skip) {
-  if (nk <= 0 || q <= 0) return hipSuccess;
-  const int NB = nblocks(n);
-  hipLaunchKernelGGL(k_basis_update, dim3(NB, q), dim3(TB), 0, s, nk, q, n, NB, V, vstride, h, W,
-                     nrm2 ? partial : nullptr, skip);
-  if (nrm2) hipLaunchKernelGGL(k_dot_final, dim3((q + 127) / 128), dim3(128), 0, s, q, q, NB, partial, nrm2, skip);
+  if (nk <= 0 || sg.S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_basis_update, dim3(sg.G), dim3(TB), 0, s, nk, sg, V, vstride, h, W, nrm2 ? partial : nullptr,
+                     skip);
+  if (nrm2)
+    hipLaunchKernelGGL(k_dot_final, dim3((sg.S + 127) / 128), dim3(128), 0, s, sg.S, sg.S, sg.nb, partial, nrm2,
+                       skip);
   return hipGetLastError();
 }
 
@@ -443,10 +472,15 @@ hipError_t launch_reorth_flag(int q, int nk, const c128* w0n2, const c128* w1n2,
   return hipGetLastError();
 }
 
-hipError_t launch_normalize(int q, long long n, const c128* nrm2, const c128* x, c128* y, double* nrm,
-                            hipStream_t s) {
-  if (q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_normalize, dim3(gx(n, 1024), q), dim3(TB), 0, s, q, n, nrm2, x, y, nrm);
+hipError_t launch_normalize(const SegDev& sg, const c128* nrm2, const c128* x, c128* y, double* nrm, hipStream_t s) {
+  if (sg.S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normalize, dim3(sg.G), dim3(TB), 0, s, sg, nrm2, x, y, nrm);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_add(const SegDev& sg, const int* active, const c128* x, c128* y, hipStream_t s) {
+  if (sg.S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_add, dim3(sg.G), dim3(TB), 0, s, sg, active, x, y);
   return hipGetLastError();
 }
 
@@ -468,9 +502,9 @@ hipError_t launch_gmres_solve_small(int q, int m, const int* jdone, const c128* 
   return hipGetLastError();
 }
 
-hipError_t launch_basis_combine(int q, long long n, const int* jdone, const c128* Z, long long zstride,
-                                const c128* y, c128* u, hipStream_t s) {
-  if (q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_basis_combine, dim3(gx(n, 1024), q), dim3(TB), 0, s, q, n, jdone, Z, zstride, y, u);
+hipError_t launch_basis_combine(const SegDev& sg, const int* jdone, const c128* Z, long long zstride, const c128* y,
+                                c128* u, hipStream_t s) {
+  if (sg.S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_basis_combine, dim3(sg.G), dim3(TB), 0, s, sg, jdone, Z, zstride, y, u);
   return hipGetLastError();
 }

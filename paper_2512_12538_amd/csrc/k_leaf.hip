@@ -27,24 +27,27 @@ __device__ __forceinline__ double2 diag_block(const OpDev& op, const BoxDev& B, 
   return mk(0.0, 0.0);
 }
 
-// Lines handled by a work-group: the chain of one half (mode 0, block = 2 leaf
-// + half) or the middle line (mode 1, block = leaf).  A line's Schur
-// complement subtracts the eliminated neighbours nb[0..nnb).
+// Lines handled by a work-group: the chain of one half (mode 0, block = 2 t
+// + half) or the middle line (mode 1, block = t) of leaf lidx[t].  A line's
+// Schur complement subtracts the eliminated neighbours nb[0..nnb).  info slot
+// of the work-group: 2 leaf + half (mode 0) or leaf (mode 1).
 struct LinePlan {
-  int leaf, count, first, step;
+  int leaf, count, first, step, slot;
 };
 
-__device__ __forceinline__ LinePlan line_plan(const BoxDev* leaves, int mode) {
+__device__ __forceinline__ LinePlan line_plan(const BoxDev* leaves, const int* lidx, int mode) {
   LinePlan P;
   if (mode == 0) {
-    P.leaf = blockIdx.x >> 1;
+    P.leaf = lidx[blockIdx.x >> 1];
     const int half = blockIdx.x & 1;
+    P.slot = 2 * P.leaf + half;
     const int nx = leaves[P.leaf].nx, m = nx >> 1;
     P.count = half ? nx - 1 - m : m;
     P.first = half ? nx - 1 : 0;
     P.step = half ? -1 : 1;
   } else {
-    P.leaf = blockIdx.x;
+    P.leaf = lidx[blockIdx.x];
+    P.slot = P.leaf;
     P.count = 1;
     P.first = leaves[P.leaf].nx >> 1;
     P.step = 1;
@@ -68,10 +71,12 @@ __device__ __forceinline__ int eliminated(const BoxDev& B, int mode, int s, int 
 // Global-memory variant for wide boxes: S_j is formed in place of G_j and
 // inverted by the work-group with Gauss-Jordan elimination and partial
 // pivoting.
-__global__ void __launch_bounds__(TB) k_leaf_factor(OpDev op, const BoxDev* __restrict__ leaves, int mode,
+__global__ void __launch_bounds__(TB) k_leaf_factor(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves,
+                                                    const int* __restrict__ lidx, int mode,
                                                     c128* __restrict__ G, int* __restrict__ info) {
-  const LinePlan P = line_plan(leaves, mode);
+  const LinePlan P = line_plan(leaves, lidx, mode);
   const BoxDev B = leaves[P.leaf];
+  const OpDev op = ops[B.prob];
   const int b = B.ny;
   const int tid = threadIdx.x;
   extern __shared__ unsigned char smem_raw[];
@@ -105,7 +110,7 @@ __global__ void __launch_bounds__(TB) k_leaf_factor(OpDev op, const BoxDev* __re
     if (tid == 0 && first == 0 && flag_before == 0 && s_flag != 0) first = j * b + s_flag;
     __syncthreads();
   }
-  if (tid == 0 && info) info[blockIdx.x] = first;
+  if (tid == 0 && info) info[P.slot] = first;
 }
 
 // The same factorisation with S_j held in the registers of an NT-thread
@@ -113,10 +118,12 @@ __global__ void __launch_bounds__(TB) k_leaf_factor(OpDev op, const BoxDev* __re
 // G_j goes to memory once per line and is read back (cache-resident) to form
 // the next line's Schur complement.
 template <int NT, int RE>
-__global__ void __launch_bounds__(NT) k_leaf_factor_reg(OpDev op, const BoxDev* __restrict__ leaves, int mode,
+__global__ void __launch_bounds__(NT) k_leaf_factor_reg(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves,
+                                                    const int* __restrict__ lidx, int mode,
                                                        c128* __restrict__ G, int* __restrict__ info) {
-  const LinePlan P = line_plan(leaves, mode);
+  const LinePlan P = line_plan(leaves, lidx, mode);
   const BoxDev B = leaves[P.leaf];
+  const OpDev op = ops[B.prob];
   const int b = B.ny, nn = b * b;
   const int tid = threadIdx.x;
   __shared__ gjr::Scratch sc;
@@ -169,41 +176,59 @@ __global__ void __launch_bounds__(NT) k_leaf_factor_reg(OpDev op, const BoxDev* 
     if (tid == 0) sc.flag = 0;
     __syncthreads();
   }
-  if (tid == 0 && info) info[blockIdx.x] = first;
+  if (tid == 0 && info) info[P.slot] = first;
 }
 
 template <int NT, int RE>
-hipError_t launch_reg(const OpDev& op, const BoxDev* leaves, int nleaf, c128* G, int* info, hipStream_t s) {
-  hipLaunchKernelGGL((k_leaf_factor_reg<NT, RE>), dim3(2 * nleaf), dim3(NT), 0, s, op, leaves, 0, G, info);
+hipError_t launch_reg(const OpDev* ops, const BoxDev* leaves, int nleaf, const int* lidx, int count, c128* G,
+                      int* info, hipStream_t s) {
+  hipLaunchKernelGGL((k_leaf_factor_reg<NT, RE>), dim3(2 * count), dim3(NT), 0, s, ops, leaves, lidx, 0, G, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_leaf_factor_reg<NT, RE>), dim3(nleaf), dim3(NT), 0, s, op, leaves, 1, G,
+  hipLaunchKernelGGL((k_leaf_factor_reg<NT, RE>), dim3(count), dim3(NT), 0, s, ops, leaves, lidx, 1, G,
                      info ? info + 2 * nleaf : nullptr);
   return hipGetLastError();
 }
 
 }  // namespace
 
+// Register-slot class of a leaf of width ny (the kernel variant that holds
+// its rows; 6: the global-memory variant).
+int leaf_factor_bucket(int ny) {
+  if (ny > 256) return 6;
+  const int G512 = 512 / ny;
+  const int re = G512 > 0 ? (ny + G512 - 1) / G512 : 1 << 30;
+  if (re <= 8) return 0;
+  if (re <= 10) return 1;
+  if (re <= 12) return 2;
+  if (re <= 16) return 3;
+  if (re <= 24) return 4;
+  if (re <= 48) return 5;
+  return 6;
+}
+
 // info: 3 nleaf ints (two chains per leaf, then the middle lines); nonzero =
-// (line * b + pivot step + 1) of the first zero pivot.
-hipError_t launch_leaf_factor(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, c128* G,
-                              int* info, hipStream_t s) {
-  if (nleaf <= 0) return hipSuccess;
+// (line * b + pivot step + 1) of the first zero pivot.  Factors the count
+// leaves lidx[0 .. count) (of nleaf), whose widths are at most max_ny.
+hipError_t launch_leaf_factor(const OpDev* ops, const BoxDev* leaves, int nleaf, const int* lidx, int count,
+                              int max_ny, c128* G, int* info, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
   if (max_ny <= 256) {
     // one row per thread, columns strided by NT / b; a narrower box needs fewer slots
     const int G512 = 512 / max_ny;
     const int re = G512 > 0 ? (max_ny + G512 - 1) / G512 : 1 << 30;
-    if (re <= 8) return launch_reg<512, 8>(op, leaves, nleaf, G, info, s);
-    if (re <= 10) return launch_reg<512, 10>(op, leaves, nleaf, G, info, s);
-    if (re <= 12) return launch_reg<512, 12>(op, leaves, nleaf, G, info, s);
-    if (re <= 16) return launch_reg<512, 16>(op, leaves, nleaf, G, info, s);
-    if (re <= 24) return launch_reg<512, 24>(op, leaves, nleaf, G, info, s);
-    if (re <= 48) return launch_reg<512, 48>(op, leaves, nleaf, G, info, s);
+    if (re <= 8) return launch_reg<512, 8>(ops, leaves, nleaf, lidx, count, G, info, s);
+    if (re <= 10) return launch_reg<512, 10>(ops, leaves, nleaf, lidx, count, G, info, s);
+    if (re <= 12) return launch_reg<512, 12>(ops, leaves, nleaf, lidx, count, G, info, s);
+    if (re <= 16) return launch_reg<512, 16>(ops, leaves, nleaf, lidx, count, G, info, s);
+    if (re <= 24) return launch_reg<512, 24>(ops, leaves, nleaf, lidx, count, G, info, s);
+    if (re <= 48) return launch_reg<512, 48>(ops, leaves, nleaf, lidx, count, G, info, s);
   }
   const size_t shm = sizeof(double2) * max_ny + (sizeof(double) + sizeof(int)) * TB + sizeof(int) * max_ny;
-  hipLaunchKernelGGL(k_leaf_factor, dim3(2 * nleaf), dim3(TB), shm, s, op, leaves, 0, G, info);
+  hipLaunchKernelGGL(k_leaf_factor, dim3(2 * count), dim3(TB), shm, s, ops, leaves, lidx, 0, G, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_leaf_factor, dim3(nleaf), dim3(TB), shm, s, op, leaves, 1, G, info ? info + 2 * nleaf : nullptr);
+  hipLaunchKernelGGL(k_leaf_factor, dim3(count), dim3(TB), shm, s, ops, leaves, lidx, 1, G,
+                     info ? info + 2 * nleaf : nullptr);
   return hipGetLastError();
 }

@@ -57,12 +57,13 @@ __device__ __forceinline__ bool owns(const BoxDev& B, int p, int q) {
 
 // Y[box][col][row] = sum over the stencil of row x of box j of
 // A~_j[x, y] (P_i X)[y]  (only owned nodes y of box i contribute).
-__global__ void __launch_bounds__(TB) k_trace(OpDev op, const BoxDev* __restrict__ boxes, int q,
+__global__ void __launch_bounds__(TB) k_trace(const OpDev* __restrict__ ops, const BoxDev* __restrict__ boxes, int q,
                                               const int2* __restrict__ rows, const long long* __restrict__ yoff,
                                               const c128* __restrict__ X, c128* __restrict__ Y) {
   const int box = blockIdx.y / q, col = blockIdx.y % q;
   const BoxDev Bi = boxes[box];
   if (col >= Bi.s) return;
+  const OpDev op = ops[Bi.prob];  // siblings share the problem
   const long long xb = Bi.voff * q + (long long)col * Bi.n;
   c128* y = Y + yoff[box] + (long long)col * Bi.tr_cnt;
   for (int r = blockIdx.x * TB + threadIdx.x; r < Bi.tr_cnt; r += gridDim.x * TB) {
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(TB) k_trace(OpDev op, const BoxDev* __restrict
 }
 
 // H[box][col][y] = sum over trace rows (j, x) reaching y of conj(A~_j[x, y]) Q[row][col]
-__global__ void __launch_bounds__(TB) k_trace_adjoint(OpDev op, const BoxDev* __restrict__ boxes, int q,
+__global__ void __launch_bounds__(TB) k_trace_adjoint(const OpDev* __restrict__ ops, const BoxDev* __restrict__ boxes, int q,
                                                       const int2* __restrict__ rows,
                                                       const int* __restrict__ seg_ptr,
                                                       const int* __restrict__ seg_y,
@@ -105,7 +106,7 @@ __global__ void __launch_bounds__(TB) k_trace_adjoint(OpDev op, const BoxDev* __
       const int2 rw = rows[Bi.tr_off + a.x];
       const BoxDev Bj = boxes[rw.x];
       const int xp = Bj.p0 + rw.y / Bj.ny, xq = Bj.q0 + rw.y % Bj.ny;
-      const double2 c = stencil_coef(op, Bj.p0, Bj.p1, Bj.q0, Bj.q1, xp, xq, a.y, a.z);
+      const double2 c = stencil_coef(ops[Bj.prob], Bj.p0, Bj.p1, Bj.q0, Bj.q1, xp, xq, a.y, a.z);
       acc = cfmac(c, qv[a.x], acc);
     }
     H[hb + seg_y[s]] = acc;
@@ -328,18 +329,18 @@ hipError_t launch_iface_gather(const BoxDev* boxes, int nbox, int q, const int* 
   return hipGetLastError();
 }
 
-hipError_t launch_trace(const OpDev& op, const BoxDev* boxes, int nbox, int q, const int2* rows,
+hipError_t launch_trace(const OpDev* ops, const BoxDev* boxes, int nbox, int q, const int2* rows,
                         const long long* yoff, const c128* X, c128* Y, hipStream_t s) {
   if (nbox <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trace, dim3(8, nbox * q), dim3(TB), 0, s, op, boxes, q, rows, yoff, X, Y);
+  hipLaunchKernelGGL(k_trace, dim3(8, nbox * q), dim3(TB), 0, s, ops, boxes, q, rows, yoff, X, Y);
   return hipGetLastError();
 }
 
-hipError_t launch_trace_adjoint(const OpDev& op, const BoxDev* boxes, int nbox, int q, const int2* rows,
+hipError_t launch_trace_adjoint(const OpDev* ops, const BoxDev* boxes, int nbox, int q, const int2* rows,
                                 const int* seg_ptr, const int* seg_y, const int4* adj, const long long* yoff,
                                 const c128* Qm, c128* H, hipStream_t s) {
   if (nbox <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_trace_adjoint, dim3(8, nbox * q), dim3(TB), 0, s, op, boxes, q, rows, seg_ptr, seg_y,
+  hipLaunchKernelGGL(k_trace_adjoint, dim3(8, nbox * q), dim3(TB), 0, s, ops, boxes, q, rows, seg_ptr, seg_y,
                      adj, yoff, Qm, H);
   return hipGetLastError();
 }

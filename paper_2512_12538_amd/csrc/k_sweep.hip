@@ -137,7 +137,8 @@ struct SlotMap {
 // back-substitution (a template argument, so profiles list the phases apart)
 template <typename T, int QB, int TM, int R, int NW, bool PF, int PHASE>
 __global__ void __launch_bounds__(64 * NW)
-    k_sweep(OpDev op, const BoxDev* __restrict__ leaves, int nunit, int nchunk, int q,
+    k_sweep(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves, const int* __restrict__ lidx,
+            int nunit, int nchunk, int q,
             const typename cvec<T>::type* __restrict__ G, const c128* __restrict__ rhs, c128* __restrict__ x,
             c128* __restrict__ edge, int edge_ld, const BoxDev* __restrict__ par, c128* __restrict__ out) {
   typedef typename cvec<T>::type CT;
@@ -158,8 +159,9 @@ __global__ void __launch_bounds__(64 * NW)
     unit = blockIdx.x / nchunk;
     chunk = blockIdx.x % nchunk;
   }
-  const int leaf = unit >> 1, half = unit & 1;
+  const int leaf = lidx[unit >> 1], half = unit & 1;
   const BoxDev B = leaves[leaf];
+  const OpDev op = ops[B.prob];
   const int b = B.ny, nx = B.nx, m = nx >> 1;
   const int n_top = m, n_bot = nx - 1 - m;
   // lines of this unit in this phase: line(s) = l0 + dl * s, s < ns
@@ -314,7 +316,7 @@ __global__ void __launch_bounds__(64 * NW)
       const long long at = oaddr[t] + (long long)j * b;
       if (phase == 1) {
         x[at] = xv;
-        if (!more) edge[((long long)unit * q + c0 + c) * edge_ld + i] = xv;
+        if (!more) edge[((long long)(2 * leaf + half) * q + c0 + c) * edge_ld + i] = xv;
       } else if (s > 0 || half == 0) {
         if (!out) {
           x[at] = xv;
@@ -335,59 +337,75 @@ __global__ void __launch_bounds__(64 * NW)
 }
 
 template <typename T, int QB, int TM, int R, int NW, bool PF>
-hipError_t launch_sweep(const OpDev& op, const BoxDev* leaves, int nleaf, int q, const typename cvec<T>::type* G,
-                        const c128* rhs, c128* x, c128* edge, int edge_ld, const BoxDev* par, c128* out,
-                        hipStream_t s) {
-  const int nchunk = (q + QB - 1) / QB, nunit = 2 * nleaf;
+hipError_t launch_sweep(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int q,
+                        const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge, int edge_ld,
+                        const BoxDev* par, c128* out, hipStream_t s) {
+  const int nchunk = (q + QB - 1) / QB, nunit = 2 * count;
   const dim3 grid(nunit * nchunk), block(64 * NW);
-  hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 1>), grid, block, 0, s, op, leaves, nunit, nchunk, q, G, rhs, x,
-                     edge, edge_ld, par, out);
+  hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 1>), grid, block, 0, s, ops, leaves, lidx, nunit, nchunk, q, G,
+                     rhs, x, edge, edge_ld, par, out);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 2>), grid, block, 0, s, op, leaves, nunit, nchunk, q, G, rhs, x,
-                     edge, edge_ld, par, out);
+  hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 2>), grid, block, 0, s, ops, leaves, lidx, nunit, nchunk, q, G,
+                     rhs, x, edge, edge_ld, par, out);
   return hipGetLastError();
 }
 
-// Column count QB per work-group: enough work-groups to cover the chip, and
-// up to four columns per group to amortise the G_j stream.
+// Column count QB per work-group: given (1, 2, 4), else enough work-groups to
+// cover the chip and up to four columns per group to amortise the G_j stream.
+// QB does not change any column's arithmetic.
 template <typename T, int TM, int R, int NW, bool PF>
-hipError_t launch_qb(const OpDev& op, const BoxDev* leaves, int nleaf, int q, const typename cvec<T>::type* G,
-                     const c128* rhs, c128* x, c128* edge, int edge_ld, const BoxDev* par, c128* out, hipStream_t s) {
-  const long long units = 2LL * nleaf;
-  if (q >= 4 && units * ((q + 3) / 4) >= 256)
-    return launch_sweep<T, 4, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, par, out, s);
-  if (q >= 2 && units * ((q + 1) / 2) >= 128)
-    return launch_sweep<T, 2, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, par, out, s);
-  return launch_sweep<T, 1, TM, R, NW, PF>(op, leaves, nleaf, q, G, rhs, x, edge, edge_ld, par, out, s);
+hipError_t launch_qb(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int q, int qb,
+                     const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge, int edge_ld,
+                     const BoxDev* par, c128* out, hipStream_t s) {
+  const long long units = 2LL * count;
+  if (qb <= 0) qb = (q >= 4 && units * ((q + 3) / 4) >= 256) ? 4 : (q >= 2 && units * ((q + 1) / 2) >= 128) ? 2 : 1;
+  if (qb == 4)
+    return launch_sweep<T, 4, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, s);
+  if (qb == 2)
+    return launch_sweep<T, 2, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, s);
+  return launch_sweep<T, 1, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, s);
 }
 
 }  // namespace
 
-// Shape buckets: R = ceil(b / 8) rounded up to the bucket (fixed by the level's
-// widest leaf, so the arithmetic of a column does not depend on q); rows
-// covered by 8 NW row groups of TM rows.
+// Shape buckets by leaf width b: R = ceil(b / 8) rounded up to the bucket,
+// rows covered by 8 NW row groups of TM rows.  A leaf's bucket depends on its
+// own width only, so a column's arithmetic is the same in any batch and for
+// any q.
+int leaf_sweep_bucket(int ny) {
+  if (ny <= 8) return 0;
+  if (ny <= 16) return 1;
+  if (ny <= 40) return 2;
+  if (ny <= 72) return 3;
+  if (ny <= 144) return 4;
+  if (ny <= 256) return 5;
+  return -1;
+}
+
 template <typename T>
-hipError_t launch_leaf_solve(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, int q,
-                             const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge,
-                             const BoxDev* par, c128* out, hipStream_t s) {
-  if (nleaf <= 0 || q <= 0) return hipSuccess;
-  if (max_ny <= 8) return launch_qb<T, 1, 1, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
-  if (max_ny <= 16) return launch_qb<T, 2, 2, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
-  if (max_ny <= 40) return launch_qb<T, 5, 5, 1, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
-  if (max_ny <= 72) return launch_qb<T, 3, 9, 3, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
-  // wider boxes: the 3 x 18 G slice stays in registers in complex64 only; the
-  // 256-wide bucket loads G at use
-  if constexpr (sizeof(T) == 4) {
-    if (max_ny <= 144) return launch_qb<T, 3, 18, 6, true>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
-  } else {
-    if (max_ny <= 144) return launch_qb<T, 3, 18, 6, false>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
+hipError_t launch_leaf_solve(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int bucket,
+                             int edge_ld, int q, int qb, const typename cvec<T>::type* G, const c128* rhs, c128* x,
+                             c128* edge, const BoxDev* par, c128* out, hipStream_t s) {
+  if (count <= 0 || q <= 0) return hipSuccess;
+  switch (bucket) {
+    case 0: return launch_qb<T, 1, 1, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
+    case 1: return launch_qb<T, 2, 2, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
+    case 2: return launch_qb<T, 5, 5, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
+    case 3: return launch_qb<T, 3, 9, 3, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
+    case 4:
+      // the 3 x 18 G slice stays in registers in complex64 only
+      return launch_qb<T, 3, 18, 6, sizeof(T) == 4>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par,
+                                                    out, s);
+    case 5:  // loads G at use
+      return launch_qb<T, 4, 32, 8, false>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
   }
-  if (max_ny <= 256) return launch_qb<T, 4, 32, 8, false>(op, leaves, nleaf, q, G, rhs, x, edge, max_ny, par, out, s);
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_leaf_solve<double>(const OpDev&, const BoxDev*, int, int, int, const c128*, const c128*,
-                                              c128*, c128*, const BoxDev*, c128*, hipStream_t);
-template hipError_t launch_leaf_solve<float>(const OpDev&, const BoxDev*, int, int, int, const c64*, const c128*,
-                                             c128*, c128*, const BoxDev*, c128*, hipStream_t);
+template hipError_t launch_leaf_solve<double>(const OpDev*, const BoxDev*, const int*, int, int, int, int, int,
+                                              const c128*, const c128*, c128*, c128*, const BoxDev*, c128*,
+                                              hipStream_t);
+template hipError_t launch_leaf_solve<float>(const OpDev*, const BoxDev*, const int*, int, int, int, int, int,
+                                             const c64*, const c128*, c128*, c128*, const BoxDev*, c128*,
+                                             hipStream_t);

@@ -18,7 +18,7 @@ constexpr int TB = 256;
 constexpr int QG = 2;
 constexpr int NXCD = 8;
 
-__global__ void __launch_bounds__(TB) k_apply_box(OpDev op, const BoxDev* __restrict__ boxes, int nbox, int gxb,
+__global__ void __launch_bounds__(TB) k_apply_box(const OpDev* __restrict__ ops, const BoxDev* __restrict__ boxes, int nbox, int gxb,
                                                   int nlog, int q, const c128* __restrict__ x,
                                                   const c128* __restrict__ b, c128* __restrict__ y, int mode) {
   const int lb = (blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
@@ -26,6 +26,7 @@ __global__ void __launch_bounds__(TB) k_apply_box(OpDev op, const BoxDev* __rest
   const int nb = lb % gxb, t = lb / gxb;
   const int box = t % nbox, cg = t / nbox;
   const BoxDev B = boxes[box];
+  const OpDev op = ops[B.prob];
   const int l = nb * TB + threadIdx.x;
   if (l >= B.n) return;
   const int a = l / B.ny, c = l - a * B.ny;
@@ -118,12 +119,13 @@ __global__ void k_f64_to_f32(const c128* __restrict__ x, c64* __restrict__ y, lo
     y[i] = to_c64(x[i]);
 }
 
-__global__ void __launch_bounds__(TB) k_rhs_g(OpDev op, const BoxDev* __restrict__ root, int q,
+__global__ void __launch_bounds__(TB) k_rhs_g(const OpDev* __restrict__ ops, const BoxDev* __restrict__ root, int q,
                                               const c128* __restrict__ f, const c128* __restrict__ g,
                                               c128* __restrict__ out) {
-  const BoxDev B = root[0];
-  const int col = blockIdx.y;
-  const long long base = (long long)col * B.n;
+  const BoxDev B = root[blockIdx.y / q];
+  const OpDev op = ops[B.prob];
+  const int col = blockIdx.y % q;
+  const long long base = B.voff * q + (long long)col * B.n;
   for (int l = blockIdx.x * TB + threadIdx.x; l < B.n; l += gridDim.x * TB) {
     const int a = l / B.ny, c = l - a * B.ny;
     const int p = B.p0 + a, qq = B.q0 + c;
@@ -144,14 +146,14 @@ inline int grid_for(long long n, int cap = 4096) {
 
 }  // namespace
 
-hipError_t launch_apply_box(const OpDev& op, const BoxDev* boxes, int nbox, int max_n, int q,
+hipError_t launch_apply_box(const OpDev* ops, const BoxDev* boxes, int nbox, int max_n, int q,
                             const c128* x, const c128* b, c128* y, int mode, hipStream_t s) {
   if (nbox <= 0 || q <= 0 || max_n <= 0) return hipSuccess;
   const int gxb = (max_n + TB - 1) / TB;
   const long long nlog = (long long)gxb * nbox * ((q + QG - 1) / QG);
   if (nlog > (1LL << 30)) return hipErrorInvalidValue;
   const long long grid = (nlog + NXCD - 1) / NXCD * NXCD;
-  hipLaunchKernelGGL(k_apply_box, dim3((unsigned)grid), dim3(TB), 0, s, op, boxes, nbox, gxb, (int)nlog, q, x, b, y,
+  hipLaunchKernelGGL(k_apply_box, dim3((unsigned)grid), dim3(TB), 0, s, ops, boxes, nbox, gxb, (int)nlog, q, x, b, y,
                      mode);
   return hipGetLastError();
 }
@@ -200,10 +202,10 @@ hipError_t launch_add_masked(const c128* x, c128* y, long long n, int q, const i
   return hipGetLastError();
 }
 
-hipError_t launch_rhs_with_impedance(const OpDev& op, const BoxDev* root, int q, const c128* f, const c128* g,
+hipError_t launch_rhs_with_impedance(const OpDev* ops, const BoxDev* root, int nroot, int q, const c128* f, const c128* g,
                                      c128* out, hipStream_t s) {
-  if (q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_rhs_g, dim3(1024, q), dim3(TB), 0, s, op, root, q, f, g, out);
+  if (q <= 0 || nroot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rhs_g, dim3(1024, nroot * q), dim3(TB), 0, s, ops, root, q, f, g, out);
   return hipGetLastError();
 }
 

@@ -10,7 +10,7 @@
 
 // ---------------------------------------------------------------- vectors / stencil (k_vec.hip)
 // y = A_box x (mode 0) or y = b - A_box x (mode 1) for every box and column of a level buffer.
-hipError_t launch_apply_box(const OpDev& op, const BoxDev* boxes, int nbox, int max_n, int q,
+hipError_t launch_apply_box(const OpDev* ops, const BoxDev* boxes, int nbox, int max_n, int q,
                             const c128* x, const c128* b, c128* y, int mode, hipStream_t s);
 // child[c][col][x] = parent[parent(c)][col][R_c x]
 hipError_t launch_gather_children(const BoxDev* child, int nchild, int max_n, const BoxDev* par, int q,
@@ -24,26 +24,35 @@ hipError_t launch_copy(const c128* x, c128* y, long long n, hipStream_t s);
 // y[col] += x[col] for the columns with active[col] != 0 (all if active is null); columns of length n
 hipError_t launch_add_masked(const c128* x, c128* y, long long n, int q, const int* active, hipStream_t s);
 hipError_t launch_f64_to_f32(const c128* x, c64* y, long long n, hipStream_t s);
-// out = f + (boundary edges at the node)/2 * g / h on the whole-domain box (1D: g/h at the ends)
-hipError_t launch_rhs_with_impedance(const OpDev& op, const BoxDev* root, int q, const c128* f, const c128* g,
+// out = f + (boundary edges at the node)/2 * g / h on every whole-domain box (1D: g/h at the ends)
+hipError_t launch_rhs_with_impedance(const OpDev* ops, const BoxDev* root, int nroot, int q, const c128* f, const c128* g,
                                      c128* out, hipStream_t s);
 
 // ---------------------------------------------------------------- leaf solves (k_leaf.hip, k_sweep.hip)
-// Two-ended block-tridiagonal factorisation of every leaf box (FP64): G_j per
-// grid line, chains from both ends to the middle line nx / 2.  info: 3 nleaf ints.
-hipError_t launch_leaf_factor(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, c128* G,
-                              int* info, hipStream_t s);
-// x = A~^{-1} rhs for every leaf box and q columns (two launches).  rhs and x
-// are distinct level buffers; edge holds 2 nleaf * q * max_ny entries of work
-// space.  G (T = double: FP64 factors, float: complex64 copy) needs 65536
-// readable entries past its end.  With par (the parent level's boxes) rhs is
-// the parent level's buffer, read in place (R_i rhs), and with out the solution
-// goes to the parent buffer on the owned nodes only (P_i x, every parent node
-// owned by one leaf); x then serves as work space.
+// Two-ended block-tridiagonal factorisation of the leaf boxes lidx[0 .. count)
+// of nleaf (FP64, widths at most max_ny): G_j per grid line, chains from both
+// ends to the middle line nx / 2.  info: 3 nleaf ints (chains 2 leaf + half,
+// then middle lines 2 nleaf + leaf); nonzero = first zero pivot.
+hipError_t launch_leaf_factor(const OpDev* ops, const BoxDev* leaves, int nleaf, const int* lidx, int count,
+                              int max_ny, c128* G, int* info, hipStream_t s);
+// Factorisation kernel class of a leaf of width ny (0..6).
+int leaf_factor_bucket(int ny);
+// Sweep shape bucket of a leaf of width ny (0..5; -1: wider than 256).
+int leaf_sweep_bucket(int ny);
+// x = A~^{-1} rhs for the leaf boxes lidx[0 .. count) (all of one shape
+// bucket) and q columns (two launches).  rhs and x are distinct level buffers;
+// edge holds 2 nleaf * q * edge_ld entries of work space (edge_ld >= every
+// leaf's width).  qb: right-hand sides per work-group (1, 2 or 4; 0 = chosen
+// from the launch size); it does not change the arithmetic.  G (T = double:
+// FP64 factors, float: complex64 copy) needs 65536 zero entries past the last
+// leaf.  With par given, the right-hand side is read in place from the parent
+// buffer (R_i r) and, with out given, the solution goes to the parent buffer on
+// the owned nodes only (P_i x, every parent node owned by one leaf); x then
+// serves as work space.
 template <typename T>
-hipError_t launch_leaf_solve(const OpDev& op, const BoxDev* leaves, int nleaf, int max_ny, int q,
-                             const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge,
-                             const BoxDev* par, c128* out, hipStream_t s);
+hipError_t launch_leaf_solve(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int bucket,
+                             int edge_ld, int q, int qb, const typename cvec<T>::type* G, const c128* rhs, c128* x,
+                             c128* edge, const BoxDev* par, c128* out, hipStream_t s);
 
 // ---------------------------------------------------------------- interface map / rSVD (k_rsvd.hip)
 // buf[box][c][iface[t]] = vals[voff[box] + c*m_in + t] for c < (use_r ? r : s); buf pre-zeroed
@@ -52,10 +61,10 @@ hipError_t launch_iface_scatter(const BoxDev* boxes, int nbox, int q, const int*
 hipError_t launch_iface_gather(const BoxDev* boxes, int nbox, int q, const int* if_idx, const long long* voff,
                                const c128* buf, c128* vals, int use_r, hipStream_t s);
 // Y[yoff[box] + c*tr_cnt + row] = (A~_j R_j P_i X)[x_row]
-hipError_t launch_trace(const OpDev& op, const BoxDev* boxes, int nbox, int q, const int2* rows,
+hipError_t launch_trace(const OpDev* ops, const BoxDev* boxes, int nbox, int q, const int2* rows,
                         const long long* yoff, const c128* X, c128* Y, hipStream_t s);
 // H[box][c][y] = sum_rows conj(A~_j[x, y]) Q[row][c]; H pre-zeroed
-hipError_t launch_trace_adjoint(const OpDev& op, const BoxDev* boxes, int nbox, int q, const int2* rows,
+hipError_t launch_trace_adjoint(const OpDev* ops, const BoxDev* boxes, int nbox, int q, const int2* rows,
                                 const int* seg_ptr, const int* seg_y, const int4* adj, const long long* yoff,
                                 const c128* Qm, c128* H, hipStream_t s);
 // Batched Householder QR: A[b] (m_b x n_b col-major) -> explicit Q in place, R (n_b x n_b); n_b <= 128
@@ -73,7 +82,7 @@ hipError_t launch_extract_owned(const BoxDev* boxes, int nbox, int max_own, int 
                                 hipStream_t s);
 
 // ---------------------------------------------------------------- coarse space (k_coarse.hip)
-hipError_t launch_galerkin_ac(const OpDev& op, const BoxDev* boxes, int nbox, const BoxDev* par, const int4* dil,
+hipError_t launch_galerkin_ac(const OpDev* ops, const BoxDev* boxes, int nbox, const BoxDev* par, const int4* dil,
                               int max_dil, int rmax, const c128* C, c128* AC, hipStream_t s);
 hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, const int4* pairs, int npairs,
                                   int rmax, const int4* dil, const c128* C, const c128* AC, c128* Ac,
@@ -98,22 +107,34 @@ hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, i
                                  hipStream_t s);
 
 // ---------------------------------------------------------------- Krylov (k_krylov.hip)
+// The systems of the outer loop (one per problem and right-hand side): system
+// b is the segment [off[b], off[b] + len[b]) of a level-0 vector.  Its
+// reductions run over nb[b] = multidot_nblocks(len[b]) chunks; the chunks of
+// all systems are numbered consecutively, chunk g = (system, index) = chunk[g].
+struct SegDev {
+  const long long* off = nullptr;
+  const int* len = nullptr;
+  const int* nb = nullptr;
+  const int2* chunk = nullptr;
+  int S = 0, G = 0, NBmax = 0;
+};
 int multidot_nblocks(long long n);
-// out[k*q + b] = sum_x conj(V_k[b][x]) W[b][x], k < nk (V_k at V + k*vstride); with wnorm also
-// out[nk*q + b] = |W[b]|^2; columns with skip[b] == 0 untouched (skip may be null);
-// partial: (nk+1)*q*NB entries
-hipError_t launch_multidot(int nk, int q, long long n, const c128* V, long long vstride, const c128* W,
+// out[k*S + b] = sum_x conj(V_k[b][x]) W[b][x], k < nk (V_k at V + k*vstride); with wnorm also
+// out[nk*S + b] = |W[b]|^2; systems with skip[b] == 0 untouched (skip may be null);
+// partial: (nk+1)*S*NBmax entries
+hipError_t launch_multidot(int nk, const SegDev& sg, const c128* V, long long vstride, const c128* W,
                            c128* partial, c128* out, hipStream_t s, int wnorm = 0, const int* skip = nullptr);
-// W[b] -= sum_k V_k[b] h[k*q + b]; if nrm2 is non-null also nrm2[b] = ||W[b]||^2 after the update
-// (partial: q*NB scratch entries); columns with skip[b] == 0 untouched
-hipError_t launch_basis_update(int nk, int q, long long n, const c128* V, long long vstride, const c128* h, c128* W,
+// W[b] -= sum_k V_k[b] h[k*S + b]; if nrm2 is non-null also nrm2[b] = ||W[b]||^2 after the update
+// (partial: S*NBmax scratch entries); systems with skip[b] == 0 untouched
+hipError_t launch_basis_update(int nk, const SegDev& sg, const c128* V, long long vstride, const c128* h, c128* W,
                                c128* partial, c128* nrm2, hipStream_t s, const int* skip = nullptr);
 // need[b] = (w1n2[b] < eta^2 w0n2[b]) (always when eta >= 1); h2[:, b] = 0 where not needed
 hipError_t launch_reorth_flag(int q, int nk, const c128* w0n2, const c128* w1n2, double eta, int* need, c128* h2,
                               hipStream_t s);
 // y[b] = x[b] / sqrt(re nrm2[b]) (zero if the norm is zero); nrm[b] = the norm
-hipError_t launch_normalize(int q, long long n, const c128* nrm2, const c128* x, c128* y, double* nrm,
-                            hipStream_t s);
+hipError_t launch_normalize(const SegDev& sg, const c128* nrm2, const c128* x, c128* y, double* nrm, hipStream_t s);
+// y[b] += x[b] for the systems with active[b] (active may be null)
+hipError_t launch_seg_add(const SegDev& sg, const int* active, const c128* x, c128* y, hipStream_t s);
 // GMRES column j for every active rhs; state = [active[q], jdone[q], iters[q]]; a rhs turns
 // inactive when |g_{j+1}| < thr[b] or iters >= maxit; any[0] = number still active
 hipError_t launch_gmres_step(int q, int j, int m, c128* H, const c128* h1, const c128* h2, const double* hnext,
@@ -121,5 +142,6 @@ hipError_t launch_gmres_step(int q, int j, int m, c128* H, const c128* h1, const
                              int* any, hipStream_t s);
 hipError_t launch_gmres_solve_small(int q, int m, const int* jdone, const c128* H, const c128* g, c128* y,
                                     hipStream_t s);
-hipError_t launch_basis_combine(int q, long long n, const int* jdone, const c128* Z, long long zstride,
-                                const c128* y, c128* u, hipStream_t s);
+// u[b] += sum_{k < jdone[b]} Z_k[b] y[k*S + b]
+hipError_t launch_basis_combine(const SegDev& sg, const int* jdone, const c128* Z, long long zstride, const c128* y,
+                                c128* u, hipStream_t s);
