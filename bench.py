@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--serving-rate", type=float, default=200.0, help="mean request arrivals per second")
     ap.add_argument("--serving-drain", type=float, default=25.0,
                     help="seconds to wait for queued requests after the stream ends")
+    ap.add_argument("--batch-count", type=int, default=512,
+                    help="independent problems of the batched measurement (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=2, help="timed steps of the batched measurement")
     return ap.parse_args()
 
 
@@ -319,6 +322,62 @@ def serving(hh, torch, precision, seconds, rate, drain=30.0, seed=11):
     }
 
 
+def batched(hh, torch, precision, count, steps, warmup=1, seed=4):
+    """The mixed batch of independent problems in one context: per step hh_setup_batch +
+    hh_build_coarse + hh_solve (one RHS per problem, GMRES(50) to 1e-8)."""
+    import workloads as W
+
+    cfg = W.WORKLOADS["helm2d_batch512"]
+    probs = W.batch_problems(count, seed)
+    dec = {m: hh.decomposition([(m, m)], cfg["overlap"]) for m in (2, 3, 4)}
+    problems = [(side, k, dec[m]) for side, k, m in probs]
+    rank, over = cfg["rank"], cfg["oversample"]
+    # inputs, resident on the device before the timed steps
+    probe = hh.hh_setup_batch(2, problems, precision=precision)
+    m_in, _, s = hh.hh_level_info(probe, 1, rank, over)
+    hh.hh_destroy(probe)
+    parts, box = [], 0
+    for p, (_, _, m) in enumerate(probs):
+        for i in range(m * m):
+            parts.append(W.omega_block(1000 + p, 1, i, int(m_in[box]), int(s[box])).reshape(-1))
+            box += 1
+    om = torch.from_numpy(np.concatenate(parts)).to("cuda")
+    del parts
+    f = torch.cat([torch.from_numpy(W.white_rhs((side + 1) ** 2, 5000 + p).reshape(-1))
+                   for p, (side, _, _) in enumerate(probs)]).to("cuda")
+    u = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    times, phases, iters = [], {"setup": [], "build_coarse": [], "solve": []}, []
+    for it in range(warmup + steps):
+        t0 = time.perf_counter()
+        ctx = hh.hh_setup_batch(2, problems, precision=precision, outer=hh.HH_GMRES, gmres_restart=50)
+        t1 = time.perf_counter()
+        hh.hh_build_coarse(ctx, 1, rank, over, om)
+        t2 = time.perf_counter()
+        info = hh.hh_solve(ctx, f, u, 1e-8, 400, raise_on_notconv=True)
+        t3 = time.perf_counter()
+        hh.hh_destroy(ctx)
+        print(f"batched {precision}: step {it} {t3 - t0:.3f} s", file=sys.stderr, flush=True)
+        if it >= warmup:
+            times.append(t3 - t0)
+            phases["setup"].append(t1 - t0)
+            phases["build_coarse"].append(t2 - t1)
+            phases["solve"].append(t3 - t2)
+            iters = [i[0] for i in info]
+    wall = float(np.sum(times))
+    by_side = {}
+    for (side, _, _), it in zip(probs, iters):
+        by_side.setdefault(side, []).append(it)
+    return {
+        "value": round(count * steps / wall, 3), "unit": "solves/s", "ms_per_step": round(1000 * wall / steps, 3),
+        "phases_ms": {k: round(1000.0 * float(np.mean(v)), 3) for k, v in phases.items()},
+        "solve_only_solves_per_s": round(count / float(np.mean(phases["solve"])), 3),
+        "gmres_iterations": {"min": int(min(iters)), "max": int(max(iters)), "mean": round(float(np.mean(iters)), 2)},
+        "iterations_mean_by_side": {str(k): round(float(np.mean(v)), 1) for k, v in sorted(by_side.items())},
+        "nodes_total": int(f.numel()), "subdomains": int(box),
+    }
+
+
 def copy_calibration(torch):
     n = 1 << 26  # 1 GiB of complex128
     x = torch.ones(n, dtype=torch.complex128, device="cuda")
@@ -397,6 +456,15 @@ def main():
                       "latency = arrival to result on the host",
             "fp64": serving(hh, torch, hh.HH_FP64, args.serving_seconds, args.serving_rate, args.serving_drain),
             "mixed": serving(hh, torch, hh.HH_MIXED, args.serving_seconds, args.serving_rate, args.serving_drain),
+        }
+    if args.batch_count > 0:
+        out["batched"] = {
+            "workload": f"helm2d_batch{args.batch_count}: {args.batch_count} independent problems, side uniform in "
+                        "{64,96,128,192,256}, k = side/6.4, m x m boxes with m uniform in {2,3,4}, 4-cell overlap, "
+                        "rank 8 per interface + 10, one white Gaussian RHS each, GMRES(50) to 1e-8; one context, "
+                        "every level of every problem in the same launches; step = setup + coarse build + solve",
+            "mixed": batched(hh, torch, hh.HH_MIXED, args.batch_count, args.batch_steps),
+            "fp64": batched(hh, torch, hh.HH_FP64, args.batch_count, args.batch_steps),
         }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_rhs)

@@ -59,6 +59,12 @@ struct Level {
   int max_dil = 0;
   int4* d_pairs = nullptr;
   int npairs = 0;
+  // work lists of the coarse restriction (chunks of owned nodes) and prolongation (node groups)
+  int2* d_rchunks = nullptr;
+  int* d_rcbase = nullptr;
+  int n_rchunks = 0;
+  int2* d_pgroups = nullptr;
+  int n_pgroups = 0;
   std::vector<double> sigma;       // per box, smax entries
   // --- this level's boxes as parents (coarse space of their problems)
   std::vector<ParentDev> hp;
@@ -91,6 +97,9 @@ struct hh_ctx {
   int outer = HH_GMRES;
   int restart = 50;
   double reorth_eta = 0.125;
+  // outer-loop systems whose preconditioner outputs are needed (device flags,
+  // nprob * q), set while GMRES iterates; null: all
+  const int* act = nullptr;
   Geometry geo;             // all problems of the batch, merged level by level
   int nprob = 1;
   std::vector<OpDev> hops;  // per problem (k points into d_k)
@@ -240,7 +249,7 @@ hh_status ensure_work(hh_ctx* c, int lo, int q) {
     if (l == c->L) HH_TRY(dalloc(c, &L.W, (size_t)2 * L.nbox * L.max_ny * q));
     if (l < c->L) {
       const Level& Ch = c->lv[l + 1];
-      L.rp_len = restrict_workspace(Ch.nbox, Ch.max_own, std::max(Ch.rmax, 1), q);
+      L.rp_len = restrict_workspace(std::max(Ch.n_rchunks, 1), std::max(Ch.rmax, 1), q);
       HH_TRY(dalloc(c, &L.RP, (size_t)L.rp_len));
     }
     L.qcap = q;
@@ -348,13 +357,14 @@ hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
     HH_CHECK(launch_scatter_owned(Ch.d, Ch.nbox, Ch.max_own, P.d, q, Ch.X, out, c->stream));
   }
   if (P.has_coarse) {
-    HH_CHECK(launch_apply_box(c->d_ops, P.d, P.nbox, P.max_n, q, out, r, P.T, 1, c->stream));
-    if (P.rp_len < restrict_workspace(Ch.nbox, Ch.max_own, Ch.rmax, q))
+    HH_CHECK(launch_apply_box(c->d_ops, P.d, P.nbox, P.max_n, q, out, r, P.T, 1, c->stream, c->act));
+    if (P.rp_len < restrict_workspace(Ch.n_rchunks, Ch.rmax, q))
       return fail(c, HH_EDEVICE, "coarse restriction workspace smaller than the launch needs");
-    HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, Ch.max_own, P.d, P.dp, Ch.rmax, q, Ch.C, P.T, P.RP, P.cvec,
-                                    c->stream));
+    HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, Ch.d_rchunks, Ch.d_rcbase, Ch.n_rchunks, P.d, P.dp, Ch.rmax, q, Ch.C,
+                                    P.T, P.RP, P.cvec, c->stream));
     HH_CHECK(launch_coarse_gemv(P.dp, P.nbox, P.max_nc, q, P.Ainv, P.cvec, P.yvec, c->stream));
-    HH_CHECK(launch_coarse_prolong(Ch.d, Ch.nbox, Ch.max_own, Ch.rmax, P.d, P.dp, q, Ch.C, P.yvec, out, c->stream));
+    HH_CHECK(launch_coarse_prolong(Ch.d, Ch.d_pgroups, Ch.n_pgroups, Ch.rmax, P.d, P.dp, q, Ch.C, P.yvec, out,
+                                   c->stream));
   }
   return HH_OK;
 }
@@ -372,10 +382,10 @@ hh_status leaf_solve(hh_ctx* c, int q, const c128* rhs, c128* x, const BoxDev* p
     const int qb = g.qb_q == q ? g.qb : 0;
     if (c->precision == HH_MIXED) {
       HH_CHECK(launch_leaf_solve<float>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G32, rhs, x, Lv.W,
-                                        par, out, c->stream));
+                                        par, out, c->act, c->stream));
     } else {
       HH_CHECK(launch_leaf_solve<double>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G, rhs, x, Lv.W,
-                                         par, out, c->stream));
+                                         par, out, c->act, c->stream));
     }
   }
   return HH_OK;
@@ -829,6 +839,23 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
       }
   Lv.max_dil = max_dil;
   Lv.npairs = (int)pairs.size();
+  {
+    std::vector<int2> rch, pgr;
+    std::vector<int> cbase(Lv.nbox, 0);
+    const int RC = restrict_chunk_nodes(), PG = prolong_group_nodes();
+    for (int i = 0; i < Lv.nbox; ++i) {
+      const BoxDev& b = Lv.hb[i];
+      cbase[i] = (int)rch.size();
+      if (b.r == 0) continue;
+      for (int k = 0; k * RC < b.n_own; ++k) rch.push_back(make_int2(i, k));
+      for (int k = 0; k * PG < b.n_own; ++k) pgr.push_back(make_int2(i, k));
+    }
+    Lv.n_rchunks = (int)rch.size();
+    Lv.n_pgroups = (int)pgr.size();
+    HH_TRY(upload(c, &Lv.d_rchunks, rch));
+    HH_TRY(upload(c, &Lv.d_rcbase, cbase));
+    HH_TRY(upload(c, &Lv.d_pgroups, pgr));
+  }
   HH_TRY(upload(c, &Lv.d_dil, dil));
   HH_TRY(upload(c, &Lv.d_pairs, pairs));
   HH_TRY(push_boxes(c, Lv));
@@ -839,7 +866,8 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   HH_TRY(dalloc(c, &P.Araw, (size_t)nc2));
   HH_TRY(dalloc(c, &P.d_piv, (size_t)P.nbox * max_nc));
   // ---------------------------------------------------------------- sketch Y = T_i Omega_i
-  HH_TRY(ensure_work(c, level - 1, std::max(smax, 1)));
+  // the sketches run smax columns through this level's boxes and the levels below
+  HH_TRY(ensure_work(c, level, std::max(smax, 1)));
   // per-box small-matrix layouts
   std::vector<int> qm(Lv.nbox), qn(Lv.nbox), bm(Lv.nbox), rr(Lv.nbox);
   std::vector<long long> yoff(Lv.nbox), soff(Lv.nbox), bhoff(Lv.nbox), voff(Lv.nbox), omoff(Lv.nbox),
@@ -1072,27 +1100,33 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     for (int k = 0; k < S; ++k) g0[(size_t)k * (m + 1)] = make_double2(beta[k], 0.0);
     GC(hipMemcpyAsync(g, g0.data(), g0.size() * sizeof(c128), hipMemcpyHostToDevice, s));
     GC(hipMemcpyAsync(state, hstate.data(), 3 * S * sizeof(int), hipMemcpyHostToDevice, s));
+    // the preconditioner and the Gram-Schmidt passes skip the systems that have stopped
+    struct ActiveScope {
+      hh_ctx* c;
+      ActiveScope(hh_ctx* c_, const int* a) : c(c_) { c->act = a; }
+      ~ActiveScope() { c->act = nullptr; }
+    } act_scope(c, state);
     for (int j = 0; j < m; ++j) {
       const c128* vj = Vb + j * vs;
       c128* zj = Zb + j * vs;
       GT(two_level(c, 0, q, vj, zj));
-      GC(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, zj, nullptr, W, 0, s));
+      GC(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, zj, nullptr, W, 0, s, state));
       // classical Gram-Schmidt twice; the second update also gives ||w||^2
       // classical Gram-Schmidt; the second pass runs for the columns whose first
       // pass cancelled by more than the factor reorth_eta (all columns when >= 1)
       const double vbytes = 16.0 * (double)n * q;
       {
         ProfScope ps(c, 2, vbytes * (j + 1 + (j + 8) / 8), 8.0 * n * q * (j + 1));
-        GC(launch_multidot(j + 1, sg, Vb, vs, W, c->d_partial, h1, s, 1));
+        GC(launch_multidot(j + 1, sg, Vb, vs, W, c->d_partial, h1, s, 1, state));
       }
       {
         ProfScope ps(c, 1, vbytes * (j + 3), 8.0 * n * q * (j + 1));
-        GC(launch_basis_update(j + 1, sg, Vb, vs, h1, W, c->d_partial, tmp, s));
+        GC(launch_basis_update(j + 1, sg, Vb, vs, h1, W, c->d_partial, tmp, s, state));
       }
-      GC(launch_reorth_flag(S, j + 1, h1 + (size_t)(j + 1) * S, tmp, c->reorth_eta, need, h2, s));
+      GC(launch_reorth_flag(S, j + 1, h1 + (size_t)(j + 1) * S, tmp, c->reorth_eta, need, h2, s, state));
       GC(launch_multidot(j + 1, sg, Vb, vs, W, c->d_partial, h2, s, 0, need));
       GC(launch_basis_update(j + 1, sg, Vb, vs, h2, W, c->d_partial, tmp, s, need));
-      GC(launch_normalize(sg, tmp, W, Vb + (j + 1) * vs, hn, s));
+      GC(launch_normalize(sg, tmp, W, Vb + (j + 1) * vs, hn, s, state));
       GC(launch_gmres_step(S, j, m, H, h1, h2, hn, cs, sn, g, est, state, thr, maxit, any, s));
       // poll the active count one step late so the stream never drains
       GC(hipMemcpyAsync(poll + (j & 1), any, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1321,7 +1355,7 @@ Footprint estimate_bytes(const hh_operator* A, const hh_decomposition* d, const 
   Geometry g;
   if (!build_geometry(A->dim, A->n_cells, d->levels, d->m, d->overlap_cells, g).empty()) return f;
   const double c16 = 16.0;
-  double op = 0.0, rhs = 0.0, work = 0.0, smax = 1.0;
+  double op = 0.0, rhs = 0.0, work = 0.0, work_below = 0.0, smax = 1.0;
   // leaf factors: FP64 during the set-up (plus the complex64 copy when mixed)
   double gl = 0.0;
   for (const HBox& b : g.levels[g.depth()]) gl += (double)b.nx() * b.ny() * b.ny();
@@ -1341,11 +1375,12 @@ Footprint estimate_bytes(const hh_operator* A, const hh_decomposition* d, const 
     }
     op += csz * c16 * 2.0 + nc * nc * c16 * 2.0;  // coarse blocks, Galerkin products, A_c^{-1}
     work += tot * c16 * 6.0 + nc * c16 * 2.0;     // level work buffers per column
+    if (l >= 1) work_below += tot * c16 * 6.0 + nc * c16 * 2.0;
   }
   rhs = work + (2.0 * restart + 3.0) * n0 * c16;  // plus the Krylov bases V, Z and work
   f.op = (size_t)op;
   f.per_rhs = (size_t)rhs;
-  f.setup = (size_t)(work * smax);  // the sketches run smax columns through every level below
+  f.setup = (size_t)(work_below * smax);  // the sketches run smax columns through levels 1 .. L
   return f;
 }
 

@@ -4,6 +4,8 @@
 // the restricted prolongation), so C^H t and C y are independent per box and
 // A_c is block-sparse: block (i, j) is non-zero only when the owned box of i
 // meets the owned box of j dilated by the 5-point stencil.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace {
@@ -212,23 +214,30 @@ __device__ __forceinline__ long long owned_to_parent(const BoxDev& B, const BoxD
 constexpr int RCH = 128;  // owned nodes per restrict work-group (split of the inner dimension)
 constexpr int KU = 8;     // inner steps whose operands are loaded before their products
 
-// part[box][chunk][a][c] = sum over the chunk's owned nodes e of conj(C[e][a]) t[c][e]
-// (a < MT 16 padded, c < q padded to 64).  Wave w: right-hand sides 16 w .. 16 w + 15
-// of the work-group's 64; MT tiles of 16 coarse vectors.  Operands of KU
-// steps of four nodes are loaded before their products, so KU (1 + MT) loads
-// per lane are in flight.
+// Restriction work items: chunk g = (child, chunk index) of RCH owned nodes,
+// the chunks of all children with a coarse space numbered consecutively
+// (child order), column group cg = 16 right-hand sides.  One wave per
+// (g, cg), items cg-fastest: with many right-hand sides the four waves of a
+// work-group share a chunk (and its C loads), with few they take consecutive
+// chunks.  part[g][a][c] = sum over the chunk's owned nodes e of conj(C[e][a])
+// t[c][e] (a < 16 MT, c < 16 ncg).  Operands of KU steps of four nodes are
+// loaded before their products, so KU (1 + MT) loads per lane are in flight.
+// A wave's arithmetic does not depend on which items share its work-group.
 template <int MT>
 __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
-                                                      int nchunk, int q, int qpad, const c128* __restrict__ C,
-                                                      const c128* __restrict__ t, c128* __restrict__ part) {
-  const int box = blockIdx.x / nchunk, chunk = blockIdx.x % nchunk;
-  const BoxDev B = child[box];
-  const int e0 = chunk * RCH;
-  if (B.r == 0 || e0 >= B.n_own) return;
-  const BoxDev P = par[B.parent];
+                                                      const int2* __restrict__ chunks, int nitems, int ncg, int q,
+                                                      const c128* __restrict__ C, const c128* __restrict__ t,
+                                                      c128* __restrict__ part) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int item = blockIdx.x * (TB / 64) + wave;
+  if (item >= nitems) return;
+  const int g = item / ncg, cg = item - g * ncg;
+  const int2 bc = chunks[g];
+  const BoxDev B = child[bc.x];
+  const int e0 = bc.y * RCH;
+  const BoxDev P = par[B.parent];
   const int m = lane & 15, kk = lane >> 4;
-  const int c = blockIdx.y * 64 + wave * 16 + m;
+  const int c = cg * 16 + m;
   const int e1 = e0 + RCH < B.n_own ? e0 + RCH : B.n_own;
   const c128* tb = t + P.voff * q + (long long)(c < q ? c : 0) * P.n;
   const c128* Cb = C + B.coff;
@@ -255,21 +264,23 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__
       for (int mt = 0; mt < MT; ++mt)
         if (mt * 16 < B.r) cmfma_ca(cv[u][mt], tv[u], re[mt], im[mt]);  // tiles past this box's rank skipped
   }
-  c128* pb = part + ((long long)box * nchunk + chunk) * (MT * 16) * qpad;
-  const int cc = blockIdx.y * 64 + wave * 16 + (lane & 15);
+  const int qpad = ncg * 16;
+  c128* pb = part + (long long)g * (MT * 16) * qpad;
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
     for (int sl = 0; sl < 4; ++sl) {
       const int a = mt * 16 + 4 * sl + (lane >> 4);
-      pb[(long long)a * qpad + cc] = mk(re[mt][sl], im[mt][sl]);
+      pb[(long long)a * qpad + c] = mk(re[mt][sl], im[mt][sl]);
     }
 }
 
-// cvec[par][c][cidx + a] = sum over chunks (in order) of part[box][chunk][a][c]
+// cvec[par][c][cidx + a] = sum over the child's chunks (in order) of part[g][a][c];
+// cbase[child] = its first chunk
 __global__ void __launch_bounds__(TB) k_restrict_sum(const BoxDev* __restrict__ child,
-                                                     const ParentDev* __restrict__ pd, int nchunk, int rpad, int q,
-                                                     int qpad, const c128* __restrict__ part, c128* __restrict__ cvec) {
+                                                     const ParentDev* __restrict__ pd, const int* __restrict__ cbase,
+                                                     int rpad, int q, int qpad, const c128* __restrict__ part,
+                                                     c128* __restrict__ cvec) {
   const int box = blockIdx.y;
   const BoxDev B = child[box];
   const int idx = blockIdx.x * TB + threadIdx.x;
@@ -277,7 +288,7 @@ __global__ void __launch_bounds__(TB) k_restrict_sum(const BoxDev* __restrict__ 
   if (a >= B.r) return;
   const ParentDev D = pd[B.parent];
   const int nch = (B.n_own + RCH - 1) / RCH;
-  const c128* pb = part + (long long)box * nchunk * rpad * qpad + (long long)a * qpad + c;
+  const c128* pb = part + (long long)cbase[box] * rpad * qpad + (long long)a * qpad + c;
   double2 s = mk(0.0, 0.0);
   for (int ch = 0; ch < nch; ++ch) s = cadd(s, pb[(long long)ch * rpad * qpad]);
   cvec[D.yoff * q + (long long)c * D.n_c + B.cidx + a] = s;
@@ -332,13 +343,20 @@ __global__ void __launch_bounds__(TB) k_coarse_gemm(const ParentDev* __restrict_
 // column slice (KU steps) before the products.
 constexpr int PR_MAXR = 128;
 
+// Work-group: (child, group of 64 owned nodes) = groups[blockIdx.x] (the
+// groups of every child with a coarse space, numbered consecutively) and 64
+// right-hand sides (blockIdx.y); NTL tiles of 16 right-hand sides per wave
+// (fewer when q is small; an output's arithmetic is the same for any NTL).
+template <int NTL>
 __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
-                                                     const ParentDev* __restrict__ pd, int ngroups, int q,
+                                                     const ParentDev* __restrict__ pd,
+                                                     const int2* __restrict__ groups, int q,
                                                      const c128* __restrict__ C, const c128* __restrict__ y,
                                                      c128* __restrict__ u) {
-  const int box = blockIdx.x / ngroups;
+  const int2 bg = groups[blockIdx.x];
+  const int box = bg.x;
   const BoxDev B = child[box];
-  const int g0 = (blockIdx.x % ngroups) * (TB / 64) * 16;
+  const int g0 = bg.y * (TB / 64) * 16;
   if (B.r == 0 || g0 >= B.n_own) return;
   const BoxDev P = par[B.parent];
   const ParentDev D = pd[B.parent];
@@ -356,9 +374,9 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ 
   if (e0 >= B.n_own) return;
   const c128* Cb = C + B.coff;
   const int en = e0 + m;
-  d4 re[4], im[4];
+  d4 re[NTL], im[NTL];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) re[t] = im[t] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NTL; ++t) re[t] = im[t] = d4{0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < B.r; k0 += 4 * KU) {
     double2 cv[KU];
 #pragma unroll
@@ -371,7 +389,7 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ 
       if (k0 + 4 * uu >= B.r) break;  // steps past this box's rank skipped
       const int a = k0 + 4 * uu + kk;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < NTL; ++t) {
         const double2 yv = a < B.r ? ys[(16 * t + m) * rs + a] : mk(0.0, 0.0);
         cmfma(yv, cv[uu], re[t], im[t]);
       }
@@ -381,7 +399,7 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ 
   if (e < B.n_own) {
     c128* ub = u + P.voff * q + owned_to_parent(B, P, e);
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < NTL; ++t)
 #pragma unroll
       for (int sl = 0; sl < 4; ++sl) {
         const int c = c0 + 16 * t + 4 * sl + (lane >> 4);
@@ -419,8 +437,10 @@ hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* 
   if (npar <= 0 || max_nc <= 0) return hipSuccess;
   hipError_t e = launch_fill_zero(info, (long long)sizeof(int) * npar, s);
   if (e != hipSuccess) return e;
+  // blocks per parent: enough for one large A_c, few when there are many parents
+  // (the elimination loop strides over the matrix)
   const long long nn = (long long)max_nc * max_nc;
-  const int gxe = gx(nn, 1024);
+  const int gxe = gx(nn, std::max(8, std::min(1024, 8192 / npar)));
   for (int kk = 0; kk < max_nc; ++kk) {
     hipLaunchKernelGGL(k_gj_pivot, dim3(npar), dim3(TB), 0, s, pars, A, piv, fcol, max_nc, kk, info);
     hipLaunchKernelGGL(k_gj_elim, dim3(gxe, npar), dim3(TB), 0, s, pars, A, fcol, max_nc, kk);
@@ -437,28 +457,34 @@ int restrict_tiles(int rmax) {
 }
 }  // namespace
 
-// The workspace holds, per child and chunk, the full padded (16 MT) x (q
-// rounded up to 64) tile that k_restrict_mfma writes.
-long long restrict_workspace(int nchild, int max_own, int rmax, int q) {
-  if (nchild <= 0 || rmax <= 0 || q <= 0) return 0;
-  const long long nchunk = (max_own + RCH - 1) / RCH;
-  const long long rpad = 16LL * restrict_tiles(rmax), qpad = (q + 63) / 64 * 64;
-  return nchild * nchunk * rpad * qpad;
+int restrict_chunk_nodes() { return RCH; }
+
+// The workspace holds, per chunk, the full padded (16 MT) x (16 ncg) tile that
+// k_restrict_mfma writes.
+long long restrict_workspace(int nchunks, int rmax, int q) {
+  if (nchunks <= 0 || rmax <= 0 || q <= 0) return 0;
+  const long long rpad = 16LL * restrict_tiles(rmax), qpad = (q + 15) / 16 * 16;
+  return nchunks * rpad * qpad;
 }
 
-hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
-                                  const ParentDev* pd, int rmax, int q, const c128* C, const c128* t, c128* part,
-                                  c128* cvec, hipStream_t s) {
-  if (nchild <= 0 || rmax <= 0 || q <= 0) return hipSuccess;
+hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* chunks, const int* cbase, int nchunks,
+                                  const BoxDev* par, const ParentDev* pd, int rmax, int q, const c128* C,
+                                  const c128* t, c128* part, c128* cvec, hipStream_t s) {
+  if (nchild <= 0 || nchunks <= 0 || rmax <= 0 || q <= 0) return hipSuccess;
   const int mt = restrict_tiles(rmax);
   if (mt == 0) return hipErrorInvalidValue;
-  const int nchunk = (max_own + RCH - 1) / RCH, qpad = (q + 63) / 64 * 64;
-  const dim3 grid(nchild * nchunk, qpad / 64);
-  if (mt == 2) hipLaunchKernelGGL(k_restrict_mfma<2>, grid, dim3(TB), 0, s, child, par, nchunk, q, qpad, C, t, part);
-  else if (mt == 4) hipLaunchKernelGGL(k_restrict_mfma<4>, grid, dim3(TB), 0, s, child, par, nchunk, q, qpad, C, t, part);
-  else hipLaunchKernelGGL(k_restrict_mfma<8>, grid, dim3(TB), 0, s, child, par, nchunk, q, qpad, C, t, part);
-  hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + TB - 1) / TB, nchild), dim3(TB), 0, s, child, pd, nchunk,
-                     16 * mt, q, qpad, part, cvec);
+  const int ncg = (q + 15) / 16;
+  const long long nitems = (long long)nchunks * ncg;
+  if (nitems > (1LL << 30)) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((nitems + TB / 64 - 1) / (TB / 64)));
+  if (mt == 2)
+    hipLaunchKernelGGL(k_restrict_mfma<2>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part);
+  else if (mt == 4)
+    hipLaunchKernelGGL(k_restrict_mfma<4>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part);
+  else
+    hipLaunchKernelGGL(k_restrict_mfma<8>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part);
+  hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + TB - 1) / TB, nchild), dim3(TB), 0, s, child, pd, cbase,
+                     16 * mt, q, ncg * 16, part, cvec);
   return hipGetLastError();
 }
 
@@ -470,14 +496,20 @@ hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, 
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, int rmax, const BoxDev* par,
+int prolong_group_nodes() { return (TB / 64) * 16; }
+
+hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ngroups, int rmax, const BoxDev* par,
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
                                  hipStream_t s) {
-  if (nchild <= 0 || q <= 0) return hipSuccess;
+  if (ngroups <= 0 || q <= 0) return hipSuccess;
   if (rmax > PR_MAXR) return hipErrorInvalidValue;
-  const int ngroups = (max_own + 63) / 64;
   const size_t shm = sizeof(double2) * 64 * (size_t)(rmax + 1);
-  hipLaunchKernelGGL(k_prolong_mfma, dim3(nchild * ngroups, (q + 63) / 64), dim3(TB), shm, s, child, par, pd, ngroups,
-                     q, C, y, u);
+  const dim3 grid(ngroups, (q + 63) / 64);
+  if (q <= 16)
+    hipLaunchKernelGGL(k_prolong_mfma<1>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u);
+  else if (q <= 32)
+    hipLaunchKernelGGL(k_prolong_mfma<2>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u);
+  else
+    hipLaunchKernelGGL(k_prolong_mfma<4>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u);
   return hipGetLastError();
 }

@@ -292,10 +292,10 @@ __global__ void __launch_bounds__(TB) k_basis_update(int nk, SegDev sg, const c1
 // factor eta: |w'|^2 < eta^2 |w|^2 (w0n2 = |w|^2 before, w1n2 = |w'|^2 after).
 // Columns that skip it get h2 = 0 so that h1 + h2 stays the projection.
 __global__ void k_reorth_flag(int q, int nk, const c128* __restrict__ w0n2, const c128* __restrict__ w1n2, double eta2,
-                              int* __restrict__ need, c128* __restrict__ h2) {
+                              int* __restrict__ need, c128* __restrict__ h2, const int* __restrict__ active) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= q) return;
-  const int nd = eta2 >= 1.0 || w1n2[b].x < eta2 * w0n2[b].x;
+  const int nd = (!active || active[b]) && (eta2 >= 1.0 || w1n2[b].x < eta2 * w0n2[b].x);
   need[b] = nd;
   if (!nd)
     for (int k = 0; k < nk; ++k) h2[k * q + b] = mk(0.0, 0.0);
@@ -303,8 +303,9 @@ __global__ void k_reorth_flag(int q, int nk, const c128* __restrict__ w0n2, cons
 
 __global__ void __launch_bounds__(TB) k_normalize(SegDev sg, const c128* __restrict__ nrm2,
                                                   const c128* __restrict__ x, c128* __restrict__ y,
-                                                  double* __restrict__ nrm) {
+                                                  double* __restrict__ nrm, const int* __restrict__ skip) {
   const Chunk ch = chunk_of(sg, blockIdx.x);
+  if (skip && !skip[ch.b]) return;
   const double nv = sqrt(fmax(nrm2[ch.b].x, 0.0));
   const double inv = nv > 0.0 ? 1.0 / nv : 0.0;
   if (ch.blk == 0 && threadIdx.x == 0 && nrm) nrm[ch.b] = nv;
@@ -466,15 +467,17 @@ hipError_t launch_basis_update(int nk, const SegDev& sg, const c128* V, long lon
 }
 
 hipError_t launch_reorth_flag(int q, int nk, const c128* w0n2, const c128* w1n2, double eta, int* need, c128* h2,
-                              hipStream_t s) {
+                              hipStream_t s, const int* active) {
   if (q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reorth_flag, dim3((q + 127) / 128), dim3(128), 0, s, q, nk, w0n2, w1n2, eta * eta, need, h2);
+  hipLaunchKernelGGL(k_reorth_flag, dim3((q + 127) / 128), dim3(128), 0, s, q, nk, w0n2, w1n2, eta * eta, need, h2,
+                     active);
   return hipGetLastError();
 }
 
-hipError_t launch_normalize(const SegDev& sg, const c128* nrm2, const c128* x, c128* y, double* nrm, hipStream_t s) {
+hipError_t launch_normalize(const SegDev& sg, const c128* nrm2, const c128* x, c128* y, double* nrm, hipStream_t s,
+                            const int* skip) {
   if (sg.S <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_normalize, dim3(sg.G), dim3(TB), 0, s, sg, nrm2, x, y, nrm);
+  hipLaunchKernelGGL(k_normalize, dim3(sg.G), dim3(TB), 0, s, sg, nrm2, x, y, nrm, skip);
   return hipGetLastError();
 }
 

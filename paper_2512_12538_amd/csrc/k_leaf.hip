@@ -201,10 +201,7 @@ int leaf_factor_bucket(int ny) {
   if (re <= 8) return 0;
   if (re <= 10) return 1;
   if (re <= 12) return 2;
-  if (re <= 16) return 3;
-  if (re <= 24) return 4;
-  if (re <= 48) return 5;
-  return 6;
+  return 6;  // wider rows would spill the register tile: the global-memory variant
 }
 
 // info: 3 nleaf ints (two chains per leaf, then the middle lines); nonzero =
@@ -213,16 +210,11 @@ int leaf_factor_bucket(int ny) {
 hipError_t launch_leaf_factor(const OpDev* ops, const BoxDev* leaves, int nleaf, const int* lidx, int count,
                               int max_ny, c128* G, int* info, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  if (max_ny <= 256) {
-    // one row per thread, columns strided by NT / b; a narrower box needs fewer slots
-    const int G512 = 512 / max_ny;
-    const int re = G512 > 0 ? (max_ny + G512 - 1) / G512 : 1 << 30;
-    if (re <= 8) return launch_reg<512, 8>(ops, leaves, nleaf, lidx, count, G, info, s);
-    if (re <= 10) return launch_reg<512, 10>(ops, leaves, nleaf, lidx, count, G, info, s);
-    if (re <= 12) return launch_reg<512, 12>(ops, leaves, nleaf, lidx, count, G, info, s);
-    if (re <= 16) return launch_reg<512, 16>(ops, leaves, nleaf, lidx, count, G, info, s);
-    if (re <= 24) return launch_reg<512, 24>(ops, leaves, nleaf, lidx, count, G, info, s);
-    if (re <= 48) return launch_reg<512, 48>(ops, leaves, nleaf, lidx, count, G, info, s);
+  switch (leaf_factor_bucket(max_ny)) {
+    case 0: return launch_reg<512, 8>(ops, leaves, nleaf, lidx, count, G, info, s);
+    case 1: return launch_reg<512, 10>(ops, leaves, nleaf, lidx, count, G, info, s);
+    case 2: return launch_reg<512, 12>(ops, leaves, nleaf, lidx, count, G, info, s);
+    default: break;
   }
   const size_t shm = sizeof(double2) * max_ny + (sizeof(double) + sizeof(int)) * TB + sizeof(int) * max_ny;
   hipLaunchKernelGGL(k_leaf_factor, dim3(2 * count), dim3(TB), shm, s, ops, leaves, lidx, 0, G, info);

@@ -140,7 +140,8 @@ __global__ void __launch_bounds__(64 * NW)
     k_sweep(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves, const int* __restrict__ lidx,
             int nunit, int nchunk, int q,
             const typename cvec<T>::type* __restrict__ G, const c128* __restrict__ rhs, c128* __restrict__ x,
-            c128* __restrict__ edge, int edge_ld, const BoxDev* __restrict__ par, c128* __restrict__ out) {
+            c128* __restrict__ edge, int edge_ld, const BoxDev* __restrict__ par, c128* __restrict__ out,
+            const int* __restrict__ active) {
   typedef typename cvec<T>::type CT;
   constexpr int phase = PHASE;
   constexpr int NT = 64 * NW, RG = 8 * NW, M0 = TM * QB;
@@ -181,6 +182,12 @@ __global__ void __launch_bounds__(64 * NW)
   const int ks = (lane & 1) | (((lane >> 4) & 1) << 1) | (((lane >> 5) & 1) << 2);
   const int rgi = wave * 8 + ((lane >> 1) & 7);
   const int c0 = chunk * QB;
+  if (active) {
+    // right-hand sides of this problem that still iterate (the others' outputs are not used)
+    bool any = false;
+    for (int c = 0; c < QB && c0 + c < q; ++c) any = any || active[B.prob * q + c0 + c];
+    if (!any) return;
+  }
   const long long base = B.voff * q;
   // right-hand side: the box's own vector, or (par given) read in place from
   // the parent's vector; node (line, i) of column c at rbase + c rcol + line rrow + i
@@ -339,15 +346,15 @@ __global__ void __launch_bounds__(64 * NW)
 template <typename T, int QB, int TM, int R, int NW, bool PF>
 hipError_t launch_sweep(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int q,
                         const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge, int edge_ld,
-                        const BoxDev* par, c128* out, hipStream_t s) {
+                        const BoxDev* par, c128* out, const int* active, hipStream_t s) {
   const int nchunk = (q + QB - 1) / QB, nunit = 2 * count;
   const dim3 grid(nunit * nchunk), block(64 * NW);
   hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 1>), grid, block, 0, s, ops, leaves, lidx, nunit, nchunk, q, G,
-                     rhs, x, edge, edge_ld, par, out);
+                     rhs, x, edge, edge_ld, par, out, active);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_sweep<T, QB, TM, R, NW, PF, 2>), grid, block, 0, s, ops, leaves, lidx, nunit, nchunk, q, G,
-                     rhs, x, edge, edge_ld, par, out);
+                     rhs, x, edge, edge_ld, par, out, active);
   return hipGetLastError();
 }
 
@@ -357,14 +364,14 @@ hipError_t launch_sweep(const OpDev* ops, const BoxDev* leaves, const int* lidx,
 template <typename T, int TM, int R, int NW, bool PF>
 hipError_t launch_qb(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int q, int qb,
                      const typename cvec<T>::type* G, const c128* rhs, c128* x, c128* edge, int edge_ld,
-                     const BoxDev* par, c128* out, hipStream_t s) {
+                     const BoxDev* par, c128* out, const int* active, hipStream_t s) {
   const long long units = 2LL * count;
   if (qb <= 0) qb = (q >= 4 && units * ((q + 3) / 4) >= 256) ? 4 : (q >= 2 && units * ((q + 1) / 2) >= 128) ? 2 : 1;
   if (qb == 4)
-    return launch_sweep<T, 4, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, s);
+    return launch_sweep<T, 4, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, active, s);
   if (qb == 2)
-    return launch_sweep<T, 2, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, s);
-  return launch_sweep<T, 1, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, s);
+    return launch_sweep<T, 2, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, active, s);
+  return launch_sweep<T, 1, TM, R, NW, PF>(ops, leaves, lidx, count, q, G, rhs, x, edge, edge_ld, par, out, active, s);
 }
 
 }  // namespace
@@ -386,26 +393,26 @@ int leaf_sweep_bucket(int ny) {
 template <typename T>
 hipError_t launch_leaf_solve(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int bucket,
                              int edge_ld, int q, int qb, const typename cvec<T>::type* G, const c128* rhs, c128* x,
-                             c128* edge, const BoxDev* par, c128* out, hipStream_t s) {
+                             c128* edge, const BoxDev* par, c128* out, const int* active, hipStream_t s) {
   if (count <= 0 || q <= 0) return hipSuccess;
   switch (bucket) {
-    case 0: return launch_qb<T, 1, 1, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
-    case 1: return launch_qb<T, 2, 2, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
-    case 2: return launch_qb<T, 5, 5, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
-    case 3: return launch_qb<T, 3, 9, 3, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
+    case 0: return launch_qb<T, 1, 1, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, active, s);
+    case 1: return launch_qb<T, 2, 2, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, active, s);
+    case 2: return launch_qb<T, 5, 5, 1, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, active, s);
+    case 3: return launch_qb<T, 3, 9, 3, true>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, active, s);
     case 4:
       // the 3 x 18 G slice stays in registers in complex64 only
       return launch_qb<T, 3, 18, 6, sizeof(T) == 4>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par,
-                                                    out, s);
+                                                    out, active, s);
     case 5:  // loads G at use
-      return launch_qb<T, 4, 32, 8, false>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, s);
+      return launch_qb<T, 4, 32, 8, false>(ops, leaves, lidx, count, q, qb, G, rhs, x, edge, edge_ld, par, out, active, s);
   }
   return hipErrorInvalidValue;
 }
 
 template hipError_t launch_leaf_solve<double>(const OpDev*, const BoxDev*, const int*, int, int, int, int, int,
                                               const c128*, const c128*, c128*, c128*, const BoxDev*, c128*,
-                                              hipStream_t);
+                                              const int*, hipStream_t);
 template hipError_t launch_leaf_solve<float>(const OpDev*, const BoxDev*, const int*, int, int, int, int, int,
                                              const c64*, const c128*, c128*, c128*, const BoxDev*, c128*,
-                                             hipStream_t);
+                                             const int*, hipStream_t);

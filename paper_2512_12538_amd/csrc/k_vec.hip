@@ -20,12 +20,19 @@ constexpr int NXCD = 8;
 
 __global__ void __launch_bounds__(TB) k_apply_box(const OpDev* __restrict__ ops, const BoxDev* __restrict__ boxes, int nbox, int gxb,
                                                   int nlog, int q, const c128* __restrict__ x,
-                                                  const c128* __restrict__ b, c128* __restrict__ y, int mode) {
+                                                  const c128* __restrict__ b, c128* __restrict__ y, int mode,
+                                                  const int* __restrict__ active) {
   const int lb = (blockIdx.x % NXCD) * (gridDim.x / NXCD) + blockIdx.x / NXCD;
   if (lb >= nlog) return;
   const int nb = lb % gxb, t = lb / gxb;
   const int box = t % nbox, cg = t / nbox;
   const BoxDev B = boxes[box];
+  const int c0 = cg * QG, c1 = c0 + QG < q ? c0 + QG : q;
+  if (active) {
+    bool any = false;
+    for (int col = c0; col < c1; ++col) any = any || active[B.prob * q + col];
+    if (!any) return;
+  }
   const OpDev op = ops[B.prob];
   const int l = nb * TB + threadIdx.x;
   if (l >= B.n) return;
@@ -40,7 +47,6 @@ __global__ void __launch_bounds__(TB) k_apply_box(const OpDev* __restrict__ ops,
   const double2 cn = hn ? stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, qq, 0, 1) : z;
   // absent neighbours read the node itself with a zero coefficient
   const int lw = hw ? l - B.ny : l, le = he ? l + B.ny : l, ls = hs ? l - 1 : l, ln = hn ? l + 1 : l;
-  const int c0 = cg * QG, c1 = c0 + QG < q ? c0 + QG : q;
 #pragma unroll
   for (int col = c0; col < c1; ++col) {
     const c128* xb = x + B.voff * q + (long long)col * B.n;
@@ -147,14 +153,14 @@ inline int grid_for(long long n, int cap = 4096) {
 }  // namespace
 
 hipError_t launch_apply_box(const OpDev* ops, const BoxDev* boxes, int nbox, int max_n, int q,
-                            const c128* x, const c128* b, c128* y, int mode, hipStream_t s) {
+                            const c128* x, const c128* b, c128* y, int mode, hipStream_t s, const int* active) {
   if (nbox <= 0 || q <= 0 || max_n <= 0) return hipSuccess;
   const int gxb = (max_n + TB - 1) / TB;
   const long long nlog = (long long)gxb * nbox * ((q + QG - 1) / QG);
   if (nlog > (1LL << 30)) return hipErrorInvalidValue;
   const long long grid = (nlog + NXCD - 1) / NXCD * NXCD;
   hipLaunchKernelGGL(k_apply_box, dim3((unsigned)grid), dim3(TB), 0, s, ops, boxes, nbox, gxb, (int)nlog, q, x, b, y,
-                     mode);
+                     mode, active);
   return hipGetLastError();
 }
 

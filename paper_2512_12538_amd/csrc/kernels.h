@@ -9,9 +9,11 @@
 #include "common.h"
 
 // ---------------------------------------------------------------- vectors / stencil (k_vec.hip)
-// y = A_box x (mode 0) or y = b - A_box x (mode 1) for every box and column of a level buffer.
+// y = A_box x (mode 0) or y = b - A_box x (mode 1) for every box and column of a level buffer;
+// with active (nprob * q flags) only the columns of active (problem, right-hand side) pairs.
 hipError_t launch_apply_box(const OpDev* ops, const BoxDev* boxes, int nbox, int max_n, int q,
-                            const c128* x, const c128* b, c128* y, int mode, hipStream_t s);
+                            const c128* x, const c128* b, c128* y, int mode, hipStream_t s,
+                            const int* active = nullptr);
 // child[c][col][x] = parent[parent(c)][col][R_c x]
 hipError_t launch_gather_children(const BoxDev* child, int nchild, int max_n, const BoxDev* par, int q,
                                   const c128* pbuf, c128* cbuf, hipStream_t s);
@@ -48,11 +50,12 @@ int leaf_sweep_bucket(int ny);
 // leaf.  With par given, the right-hand side is read in place from the parent
 // buffer (R_i r) and, with out given, the solution goes to the parent buffer on
 // the owned nodes only (P_i x, every parent node owned by one leaf); x then
-// serves as work space.
+// serves as work space.  active (nullable, nprob * q flags): right-hand sides
+// whose outputs are needed; a work-group whose columns are all inactive exits.
 template <typename T>
 hipError_t launch_leaf_solve(const OpDev* ops, const BoxDev* leaves, const int* lidx, int count, int bucket,
                              int edge_ld, int q, int qb, const typename cvec<T>::type* G, const c128* rhs, c128* x,
-                             c128* edge, const BoxDev* par, c128* out, hipStream_t s);
+                             c128* edge, const BoxDev* par, c128* out, const int* active, hipStream_t s);
 
 // ---------------------------------------------------------------- interface map / rSVD (k_rsvd.hip)
 // buf[box][c][iface[t]] = vals[voff[box] + c*m_in + t] for c < (use_r ? r : s); buf pre-zeroed
@@ -92,17 +95,23 @@ hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, co
 hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, c128* fcol, int* info,
                              hipStream_t s);
 // cvec[par][c][cidx + a] = C_child[a]^H t[par][c][owned nodes of child]: FP64
-// matrix-core products over chunks of owned nodes into `part`
-// (restrict_workspace entries), then an ordered sum over the chunks.
-long long restrict_workspace(int nchild, int max_own, int rmax, int q);
-hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, int max_own, const BoxDev* par,
-                                  const ParentDev* pd, int rmax, int q, const c128* C, const c128* t, c128* part,
-                                  c128* cvec, hipStream_t s);
+// matrix-core products over chunks of restrict_chunk_nodes() owned nodes into
+// `part` (restrict_workspace(nchunks, rmax, q) entries), then an ordered sum
+// over each child's chunks.  chunks[g] = (child, chunk index) for the chunks of
+// every child with a coarse space, child-major; cbase[child] = its first chunk.
+int restrict_chunk_nodes();
+long long restrict_workspace(int nchunks, int rmax, int q);
+hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* chunks, const int* cbase, int nchunks,
+                                  const BoxDev* par, const ParentDev* pd, int rmax, int q, const c128* C,
+                                  const c128* t, c128* part, c128* cvec, hipStream_t s);
 // y[par][c] = A_c^{-1} cvec[par][c] (FP64 matrix cores)
 hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, const c128* Ainv,
                               const c128* cvec, c128* y, hipStream_t s);
-// u[par][c][owned nodes of child] += C_child y[par][c][cidx ..] (FP64 matrix cores)
-hipError_t launch_coarse_prolong(const BoxDev* child, int nchild, int max_own, int rmax, const BoxDev* par,
+// u[par][c][owned nodes of child] += C_child y[par][c][cidx ..] (FP64 matrix cores);
+// groups[g] = (child, group of prolong_group_nodes() owned nodes) for every child
+// with a coarse space
+int prolong_group_nodes();
+hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ngroups, int rmax, const BoxDev* par,
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
                                  hipStream_t s);
 
@@ -128,11 +137,14 @@ hipError_t launch_multidot(int nk, const SegDev& sg, const c128* V, long long vs
 // (partial: S*NBmax scratch entries); systems with skip[b] == 0 untouched
 hipError_t launch_basis_update(int nk, const SegDev& sg, const c128* V, long long vstride, const c128* h, c128* W,
                                c128* partial, c128* nrm2, hipStream_t s, const int* skip = nullptr);
-// need[b] = (w1n2[b] < eta^2 w0n2[b]) (always when eta >= 1); h2[:, b] = 0 where not needed
+// need[b] = active[b] and (w1n2[b] < eta^2 w0n2[b]) (always when eta >= 1; active may be null);
+// h2[:, b] = 0 where not needed
 hipError_t launch_reorth_flag(int q, int nk, const c128* w0n2, const c128* w1n2, double eta, int* need, c128* h2,
-                              hipStream_t s);
-// y[b] = x[b] / sqrt(re nrm2[b]) (zero if the norm is zero); nrm[b] = the norm
-hipError_t launch_normalize(const SegDev& sg, const c128* nrm2, const c128* x, c128* y, double* nrm, hipStream_t s);
+                              hipStream_t s, const int* active = nullptr);
+// y[b] = x[b] / sqrt(re nrm2[b]) (zero if the norm is zero); nrm[b] = the norm; systems with
+// skip[b] == 0 untouched (skip may be null)
+hipError_t launch_normalize(const SegDev& sg, const c128* nrm2, const c128* x, c128* y, double* nrm, hipStream_t s,
+                            const int* skip = nullptr);
 // y[b] += x[b] for the systems with active[b] (active may be null)
 hipError_t launch_seg_add(const SegDev& sg, const int* active, const c128* x, c128* y, hipStream_t s);
 // GMRES column j for every active rhs; state = [active[q], jdone[q], iters[q]]; a rhs turns

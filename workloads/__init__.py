@@ -23,6 +23,7 @@ __all__ = [
     "gaussian_random_field",
     "wavenumber_grf",
     "omega_block",
+    "batch_problems",
     "WORKLOADS",
 ]
 
@@ -108,6 +109,17 @@ def omega_block(seed: int, level: int, box: int, m_in: int, s: int) -> np.ndarra
 
 
 # Workload definitions (sizes and seeds of the synthetic problems).
+def batch_problems(count: int, seed: int):
+    """The mixed batch of independent 2D problems: per problem a grid side drawn
+    uniformly from {64, 96, 128, 192, 256}, k = side / 6.4 (about 40 points per
+    wavelength) and an m x m split with m uniform in {2, 3, 4}.  Returns a list of
+    (side, k, m)."""
+    g = _rng(seed, 7)
+    sides = g.choice(np.array([64, 96, 128, 192, 256]), size=count)
+    ms = g.integers(2, 5, size=count)
+    return [(int(s), float(s) / 6.4, int(m)) for s, m in zip(sides, ms)]
+
+
 WORKLOADS = {
     # 1D, k = 20*pi, 2000 interior + 2 boundary nodes, two subdomains
     # overlapping by 20 cells, one interface mode per subdomain.
@@ -121,6 +133,9 @@ WORKLOADS = {
     "helm2d_n1024_grf_3lvl": dict(dim=2, n_cells=1024, k=160.0, k_amp=0.3, k_corr=0.1,
                                   m=[(2, 2), (2, 2), (2, 2)], overlap=[8, 8, 8],
                                   rank=16, oversample=10, rhs="smooth"),
+    # 512 independent problems (batch_problems), 4-cell overlap, rank 8 per
+    # interface + 10, white Gaussian RHS, complex64 local solves.
+    "helm2d_batch512": dict(dim=2, count=512, overlap=[4], rank=8, oversample=10, rhs="white"),
 }
 
 
