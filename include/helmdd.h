@@ -87,6 +87,12 @@ typedef struct {
   int32_t full_reorth;   /* GMRES Arnoldi: 1 = classical Gram-Schmidt twice at every step;
                             0 = second pass only where the first cancelled ||w|| by more than 8x */
   void* stream;          /* hipStream_t, or null */
+  int32_t autotune;      /* 1: on the first solve with a given nrhs, time the leaf sweep with 1, 2 and 4
+                            right-hand sides per work-group for every leaf shape and keep the fastest
+                            (the arithmetic of a column does not depend on it) */
+  int32_t graphs;        /* 1: from the second GMRES solve with a given nrhs on, each Arnoldi step is
+                            captured once into a HIP graph and replayed (stream must not be null);
+                            results are bit-identical to the eager steps */
 } hh_options;
 
 typedef struct {
@@ -113,6 +119,14 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
  * problems differ in dim or depth).  hh_setup is hh_setup_batch with nprob = 1. */
 hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposition* d, const hh_options* o,
                          hh_ctx** out);
+
+/* The leaf sweep plan: the leaves grouped by shape bucket (0..5: widths up
+ * to 8, 16, 40, 72, 144, 256 nodes), per group its bucket, leaf count, widest
+ * leaf, and the right-hand sides per work-group the autotuner chose (qb) for
+ * nrhs = tuned_for (0 when not tuned: chosen from the launch size).  Arrays
+ * have ngroups entries (at most 6); any may be null. */
+hh_status hh_sweep_plan(const hh_ctx* c, int32_t* ngroups, int32_t* bucket, int32_t* count, int32_t* max_width,
+                        int32_t* qb, int32_t* tuned_for);
 
 /* nprob, and per problem its node count n_p and the offset (in complex entries,
  * per right-hand side) of its block: problem p's column c starts at

@@ -44,7 +44,8 @@ class hh_decomposition(ctypes.Structure):
 
 class hh_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("outer", ctypes.c_int32),
-                ("gmres_restart", ctypes.c_int32), ("full_reorth", ctypes.c_int32), ("stream", ctypes.c_void_p)]
+                ("gmres_restart", ctypes.c_int32), ("full_reorth", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("autotune", ctypes.c_int32), ("graphs", ctypes.c_int32)]
 
 
 class hh_solve_info(ctypes.Structure):
@@ -96,6 +97,7 @@ def _load():
         "hh_setup_batch": [i32, ctypes.POINTER(hh_operator), ctypes.POINTER(hh_decomposition),
                            ctypes.POINTER(hh_options), ctypes.POINTER(P)],
         "hh_problem_layout": [P, P, P, P],
+        "hh_sweep_plan": [P, P, P, P, P, P, P],
         "hh_level_info": [P, i32, i32, i32, P, P, P, P],
         "hh_build_coarse": [P, i32, i32, i32, P],
         "hh_solve": [P, i32, P, P, P, ctypes.c_double, i32, P],
@@ -209,7 +211,7 @@ def _vectors(ctx: Context, t: torch.Tensor, name: str) -> int:
 
 def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int = HH_FP64,
              outer: int = HH_GMRES, gmres_restart: int = 50, stream: torch.cuda.Stream | None = None,
-             full_reorth: bool = False):
+             full_reorth: bool = False, autotune: bool = False, graphs: bool = False):
     """Returns a Context.  ``k`` is a float or a host array of node wavenumbers."""
     op = hh_operator()
     op.dim = dim
@@ -227,6 +229,8 @@ def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int
     opts.outer = outer
     opts.gmres_restart = gmres_restart
     opts.full_reorth = 1 if full_reorth else 0
+    opts.autotune = 1 if autotune else 0
+    opts.graphs = 1 if graphs else 0
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = ctypes.c_void_p(st.cuda_stream)
     ctx = ctypes.c_void_p()
@@ -238,7 +242,8 @@ def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int
 
 
 def hh_setup_batch(dim: int, problems, precision: int = HH_FP64, outer: int = HH_GMRES, gmres_restart: int = 50,
-                   stream: torch.cuda.Stream | None = None, full_reorth: bool = False):
+                   stream: torch.cuda.Stream | None = None, full_reorth: bool = False, autotune: bool = False,
+                   graphs: bool = False):
     """Independent problems in one context.  ``problems``: sequence of (n_cells, k, decomposition),
     k a float or a host array of node wavenumbers.  Returns a Context (see Context.pack/unpack)."""
     nprob = len(problems)
@@ -264,6 +269,8 @@ def hh_setup_batch(dim: int, problems, precision: int = HH_FP64, outer: int = HH
     opts.outer = outer
     opts.gmres_restart = gmres_restart
     opts.full_reorth = 1 if full_reorth else 0
+    opts.autotune = 1 if autotune else 0
+    opts.graphs = 1 if graphs else 0
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = ctypes.c_void_p(st.cuda_stream)
     ctx = ctypes.c_void_p()
@@ -278,6 +285,15 @@ def hh_setup_batch(dim: int, problems, precision: int = HH_FP64, outer: int = HH
         hh_destroy(c)
         raise RuntimeError("problem layout differs from the binding's")
     return c
+
+
+def hh_sweep_plan(ctx):
+    """The leaf sweep plan: list of dicts (bucket, leaves, max_width, qb, tuned_for) per shape group."""
+    arrs = [np.zeros(8, np.int32) for _ in range(5)]
+    ng = ctypes.c_int32()
+    _check(_lib.hh_sweep_plan(ctx, ctypes.byref(ng), *[a.ctypes.data_as(ctypes.c_void_p) for a in arrs]), ctx)
+    keys = ["bucket", "leaves", "max_width", "qb", "tuned_for"]
+    return [{k: int(a[i]) for k, a in zip(keys, arrs)} for i in range(ng.value)]
 
 
 def hh_level_info(ctx, level: int, rank: int = 0, oversample: int = 0):

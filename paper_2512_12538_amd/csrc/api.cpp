@@ -105,6 +105,21 @@ struct hh_ctx {
   std::vector<OpDev> hops;  // per problem (k points into d_k)
   OpDev* d_ops = nullptr;
   double* d_k = nullptr;
+  bool autotune = false;  // time the sweep's column-group widths on the first use of a q
+  bool graphs = false;    // replay captured Arnoldi steps (from the second solve with a q on)
+  bool capturing = false;
+  int gw_maxit = -1;      // maxit the step graphs were captured with
+  long long epoch = 0;    // bumped whenever a buffer or table used inside a captured step changes
+  // persistent GMRES work space (the captured steps refer to it) and the step graphs
+  struct Gmres {
+    int q = 0, m = 0, solves = 0;
+    long long epoch = -1;
+    c128 *Vb = nullptr, *Zb = nullptr, *W = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
+    c128 *h1 = nullptr, *h2 = nullptr, *tmp = nullptr, *y = nullptr;
+    double *hn = nullptr, *est = nullptr, *thr = nullptr;
+    int *state = nullptr, *any = nullptr, *need = nullptr;
+    std::vector<hipGraphExec_t> exec;
+  } gw;
   // outer-loop systems (problem, right-hand side) for sg_q right-hand sides
   SegDev sg;
   int sg_q = 0;
@@ -232,6 +247,7 @@ hh_status ensure_work(hh_ctx* c, int lo, int q) {
   for (int l = lo; l <= c->L; ++l) {
     Level& L = c->lv[l];
     if (L.qcap >= q) continue;
+    ++c->epoch;
     for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec, &L.W, &L.RP}) {
       dfree(c, *b);
       *b = nullptr;
@@ -273,6 +289,7 @@ hh_status ensure_poll(hh_ctx* c) {
 
 hh_status ensure_partial(hh_ctx* c, size_t count) {
   if (c->partial_cap >= count) return HH_OK;
+  ++c->epoch;
   dfree(c, c->d_partial);
   c->d_partial = nullptr;
   HH_TRY(dalloc(c, &c->d_partial, count));
@@ -298,7 +315,7 @@ struct ProfScope {
   double bytes, flops;
   hipEvent_t a = nullptr;
   ProfScope(hh_ctx* c_, int fam_, double bytes_, double flops_) : c(c_), fam(fam_), bytes(bytes_), flops(flops_) {
-    if (c->prof && (a = prof_event(c))) (void)hipEventRecord(a, c->stream);
+    if (c->prof && !c->capturing && (a = prof_event(c))) (void)hipEventRecord(a, c->stream);
   }
   ~ProfScope() {
     if (!a) return;
@@ -377,16 +394,44 @@ hh_status leaf_solve(hh_ctx* c, int q, const c128* rhs, c128* x, const BoxDev* p
   if (c->prof) leaf_solve_cost(Lv, q, c->precision == HH_MIXED ? 8 : 16, bytes, flops);
   ProfScope ps(c, 0, bytes, flops);
   if (Lv.qcap < q) return fail(c, HH_EDEVICE, "leaf solve work space smaller than the launch needs");
-  for (LeafGroup& g : Lv.sweep_groups) {
+  auto launch = [&](const LeafGroup& g, int qb) {
     const int* lidx = Lv.d_sweep_order + g.start;
-    const int qb = g.qb_q == q ? g.qb : 0;
-    if (c->precision == HH_MIXED) {
-      HH_CHECK(launch_leaf_solve<float>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G32, rhs, x, Lv.W,
-                                        par, out, c->act, c->stream));
-    } else {
-      HH_CHECK(launch_leaf_solve<double>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G, rhs, x, Lv.W,
-                                         par, out, c->act, c->stream));
+    if (c->precision == HH_MIXED)
+      return launch_leaf_solve<float>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G32, rhs, x, Lv.W,
+                                      par, out, c->act, c->stream);
+    return launch_leaf_solve<double>(c->d_ops, Lv.d, lidx, g.count, g.key, Lv.max_ny, q, qb, c->G, rhs, x, Lv.W, par,
+                                     out, c->act, c->stream);
+  };
+  for (LeafGroup& g : Lv.sweep_groups) {
+    if (c->autotune && !c->capturing && g.qb_q != q) {
+      // the autotuner: time every column-group width on this launch's own data
+      // (each computes the same result, so the trial runs are harmless) and keep
+      // the fastest for this q
+      hipEvent_t e0 = prof_event(c), e1 = prof_event(c);
+      if (!e0 || !e1) return device_fail(c, "hipEventCreate", hipErrorOutOfMemory);
+      float best = 3.0e38f;
+      int bq = 0;
+      for (int qb : {1, 2, 4}) {
+        if (qb > 1 && qb > q) continue;
+        for (int rep = 0; rep < 2; ++rep) {
+          HH_CHECK(hipEventRecord(e0, c->stream));
+          HH_CHECK(launch(g, qb));
+          HH_CHECK(hipEventRecord(e1, c->stream));
+          HH_CHECK(hipEventSynchronize(e1));
+          float ms = 0.0f;
+          HH_CHECK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < best) {
+            best = ms;
+            bq = qb;
+          }
+        }
+      }
+      c->ev_pool.push_back(e0);
+      c->ev_pool.push_back(e1);
+      g.qb = bq;
+      g.qb_q = q;
     }
+    HH_CHECK(launch(g, g.qb_q == q ? g.qb : 0));
   }
   return HH_OK;
 }
@@ -422,6 +467,7 @@ hh_status check_built(hh_ctx* c) {
 // problem p, the segment of level-0 box p that holds it.
 hh_status ensure_segs(hh_ctx* c, int q) {
   if (c->sg_q == q) return HH_OK;
+  ++c->epoch;
   const Level& R = c->lv[0];
   const int S = R.nbox * q;
   std::vector<long long> off(S);
@@ -489,6 +535,8 @@ const char* hh_last_error(const hh_ctx* c) { return c ? c->err.c_str() : "null c
 hh_status hh_destroy(hh_ctx* c) {
   if (!c) return HH_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (hipGraphExec_t e : c->gw.exec)
+    if (e) (void)hipGraphExecDestroy(e);
   for (int i = 0; i < 2; ++i)
     if (c->poll_ev[i]) (void)hipEventDestroy(c->poll_ev[i]);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -542,6 +590,8 @@ hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposi
     c->outer = o->outer == HH_STATIONARY ? HH_STATIONARY : HH_GMRES;
     c->restart = o->gmres_restart > 0 ? std::min(o->gmres_restart, 120) : 50;
     c->reorth_eta = o->full_reorth ? 2.0 : 0.125;
+    c->autotune = o->autotune != 0;
+    c->graphs = o->graphs != 0;
   }
   if (!merge_geometries(parts, c->geo).empty()) {
     delete c;
@@ -703,6 +753,22 @@ hh_status hh_problem_layout(const hh_ctx* c, int32_t* nprob, int64_t* n_nodes, i
   return HH_OK;
 }
 
+hh_status hh_sweep_plan(const hh_ctx* c, int32_t* ngroups, int32_t* bucket, int32_t* count, int32_t* max_width,
+                        int32_t* qb, int32_t* tuned_for) {
+  if (!c) return HH_EINVAL;
+  const Level& Lv = c->lv[c->L];
+  if (ngroups) *ngroups = (int32_t)Lv.sweep_groups.size();
+  for (size_t i = 0; i < Lv.sweep_groups.size(); ++i) {
+    const LeafGroup& g = Lv.sweep_groups[i];
+    if (bucket) bucket[i] = g.key;
+    if (count) count[i] = g.count;
+    if (max_width) max_width[i] = g.max_ny;
+    if (qb) qb[i] = g.qb;
+    if (tuned_for) tuned_for[i] = g.qb_q;
+  }
+  return HH_OK;
+}
+
 hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversample, const void* omega) {
   HH_TRY(check_usable(c));
   if (level < 1 || level > c->L || rank < 0 || oversample < 0)
@@ -728,6 +794,7 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   if (rmax > 0 && !omega) return fail(c, HH_EINVAL, "omega is required when the rank is positive");
   // invalidate every coarser level: their sub-solves change with this one
   for (int l = 1; l < level; ++l) c->lv[l].built = false;
+  ++c->epoch;
   Lv.rank = rank;
   Lv.rmax = rmax;
   Lv.smax = smax;
@@ -1013,6 +1080,134 @@ hh_status hh_precondition(hh_ctx* c, int32_t nrhs, const void* r, void* z) {
 
 namespace {
 
+void drop_graphs(hh_ctx* c) {
+  bool any = false;
+  for (hipGraphExec_t e : c->gw.exec) any = any || e != nullptr;
+  if (any) (void)hipStreamSynchronize(c->stream);  // no replay still in flight
+  for (hipGraphExec_t& e : c->gw.exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  c->gw.exec.clear();
+}
+
+// The persistent GMRES work space for q right-hand sides and restart m (the
+// captured Arnoldi steps refer to these buffers).
+hh_status ensure_gmres(hh_ctx* c, int q, int m) {
+  hh_ctx::Gmres& w = c->gw;
+  if (w.q == q && w.m == m) return HH_OK;
+  drop_graphs(c);
+  for (void* p : std::initializer_list<void*>{w.Vb, w.Zb, w.W, w.H, w.cs, w.sn, w.g, w.h1, w.h2, w.tmp, w.y, w.hn,
+                                              w.est, w.thr, w.state, w.any, w.need})
+    dfree(c, p);
+  w = hh_ctx::Gmres();
+  ++c->epoch;
+  const long long n = c->lv[0].total;
+  const int S = c->sg.S;
+  HH_TRY(dalloc(c, &w.Vb, (size_t)(m + 1) * q * n));
+  HH_TRY(dalloc(c, &w.Zb, (size_t)m * q * n));
+  HH_TRY(dalloc(c, &w.W, (size_t)q * n));
+  HH_TRY(dalloc(c, &w.H, (size_t)S * (m + 1) * m));
+  HH_TRY(dalloc(c, &w.cs, (size_t)S * m));
+  HH_TRY(dalloc(c, &w.sn, (size_t)S * m));
+  HH_TRY(dalloc(c, &w.g, (size_t)S * (m + 1)));
+  HH_TRY(dalloc(c, &w.h1, (size_t)S * (m + 2)));
+  HH_TRY(dalloc(c, &w.need, (size_t)S));
+  HH_TRY(dalloc(c, &w.h2, (size_t)S * (m + 1)));
+  HH_TRY(dalloc(c, &w.tmp, (size_t)S * (m + 1)));
+  HH_TRY(dalloc(c, &w.y, (size_t)S * m));
+  HH_TRY(dalloc(c, &w.hn, (size_t)S));
+  HH_TRY(dalloc(c, &w.est, (size_t)S));
+  HH_TRY(dalloc(c, &w.thr, (size_t)S));
+  HH_TRY(dalloc(c, &w.state, (size_t)3 * S));
+  HH_TRY(dalloc(c, &w.any, (size_t)2));
+  w.q = q;
+  w.m = m;
+  return HH_OK;
+}
+
+void release_gmres(hh_ctx* c) {
+  hh_ctx::Gmres& w = c->gw;
+  drop_graphs(c);
+  for (void* p : std::initializer_list<void*>{w.Vb, w.Zb, w.W, w.H, w.cs, w.sn, w.g, w.h1, w.h2, w.tmp, w.y, w.hn,
+                                              w.est, w.thr, w.state, w.any, w.need})
+    dfree(c, p);
+  w = hh_ctx::Gmres();
+  ++c->epoch;
+}
+
+// One Arnoldi step j for every system: z_j = B v_j, w = A z_j, Gram-Schmidt
+// (a second pass where the first cancelled more than reorth_eta), v_{j+1}, and
+// the Givens update of the Hessenberg column with the stopping test.  Device
+// work only (no allocation, no host synchronisation), so it can be captured.
+hh_status arnoldi_step(hh_ctx* c, int q, int j, int maxit) {
+  hh_ctx::Gmres& w = c->gw;
+  const SegDev& sg = c->sg;
+  const int S = sg.S, m = w.m;
+  const long long n = c->lv[0].total, vs = (long long)q * n;
+  hipStream_t s = c->stream;
+  const c128* vj = w.Vb + j * vs;
+  c128* zj = w.Zb + j * vs;
+  HH_TRY(two_level(c, 0, q, vj, zj));
+  HH_CHECK(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, zj, nullptr, w.W, 0, s,
+                            w.state));
+  const double vbytes = 16.0 * (double)n * q;
+  {
+    ProfScope ps(c, 2, vbytes * (j + 1 + (j + 8) / 8), 8.0 * n * q * (j + 1));
+    HH_CHECK(launch_multidot(j + 1, sg, w.Vb, vs, w.W, c->d_partial, w.h1, s, 1, w.state));
+  }
+  {
+    ProfScope ps(c, 1, vbytes * (j + 3), 8.0 * n * q * (j + 1));
+    HH_CHECK(launch_basis_update(j + 1, sg, w.Vb, vs, w.h1, w.W, c->d_partial, w.tmp, s, w.state));
+  }
+  HH_CHECK(launch_reorth_flag(S, j + 1, w.h1 + (size_t)(j + 1) * S, w.tmp, c->reorth_eta, w.need, w.h2, s, w.state));
+  HH_CHECK(launch_multidot(j + 1, sg, w.Vb, vs, w.W, c->d_partial, w.h2, s, 0, w.need));
+  HH_CHECK(launch_basis_update(j + 1, sg, w.Vb, vs, w.h2, w.W, c->d_partial, w.tmp, s, w.need));
+  HH_CHECK(launch_normalize(sg, w.tmp, w.W, w.Vb + (j + 1) * vs, w.hn, s, w.state));
+  HH_CHECK(launch_gmres_step(S, j, m, w.H, w.h1, w.h2, w.hn, w.cs, w.sn, w.g, w.est, w.state, w.thr, maxit, w.any, s));
+  return HH_OK;
+}
+
+// Enqueues Arnoldi step j: eagerly, or (graphs on, from the second solve with
+// this work space on) by replaying its captured graph, capturing it first.
+hh_status run_step(hh_ctx* c, int q, int j, int maxit) {
+  hh_ctx::Gmres& w = c->gw;
+  const bool use = c->graphs && w.solves > 0 && c->stream != nullptr && !c->prof;
+  if (!use) return arnoldi_step(c, q, j, maxit);
+  if (w.epoch != c->epoch) {
+    drop_graphs(c);
+    w.epoch = c->epoch;
+  }
+  // maxit is a kernel argument of the step: graphs are kept for one value
+  if ((int)w.exec.size() != w.m + 1) {
+    drop_graphs(c);
+    w.exec.assign(w.m + 1, nullptr);
+  }
+  if (c->gw_maxit != maxit) {
+    drop_graphs(c);
+    w.exec.assign(w.m + 1, nullptr);
+    c->gw_maxit = maxit;
+  }
+  if (!w.exec[j]) {
+    HH_CHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    c->capturing = true;
+    const hh_status st = arnoldi_step(c, q, j, maxit);
+    c->capturing = false;
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->stream, &graph);
+    if (st != HH_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return device_fail(c, "hipStreamEndCapture", e);
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return device_fail(c, "hipGraphInstantiate", ei);
+    w.exec[j] = exec;
+  }
+  HH_CHECK(hipGraphLaunch(w.exec[j], c->stream));
+  return HH_OK;
+}
+
 // Right-preconditioned restarted GMRES (flexible form: Z_j = B v_j kept) for
 // every outer-loop system at once; q right-hand sides per problem, S systems.
 hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit, const std::vector<double>& nb,
@@ -1022,57 +1217,15 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
   const int S = sg.S;
   const int m = std::max(1, std::min(c->restart, std::max(maxit, 1)));
   hipStream_t s = c->stream;
-  c128 *Vb = nullptr, *Zb = nullptr, *W = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr;
-  c128 *h1 = nullptr, *h2 = nullptr, *tmp = nullptr, *y = nullptr;
-  double *hn = nullptr, *est = nullptr, *thr = nullptr;
-  int *state = nullptr, *any = nullptr, *need = nullptr;
-  auto cleanup = [&]() {
-    for (void* p :
-         std::initializer_list<void*>{Vb, Zb, W, H, cs, sn, g, h1, h2, tmp, y, hn, est, thr, state, any, need})
-      dfree(c, p);
-  };
-  hh_status st = HH_OK;
-  do {
-    if ((st = dalloc(c, &Vb, (size_t)(m + 1) * q * n)) != HH_OK) break;
-    if ((st = dalloc(c, &Zb, (size_t)m * q * n)) != HH_OK) break;
-    if ((st = dalloc(c, &W, (size_t)q * n)) != HH_OK) break;
-    if ((st = dalloc(c, &H, (size_t)S * (m + 1) * m)) != HH_OK) break;
-    if ((st = dalloc(c, &cs, (size_t)S * m)) != HH_OK) break;
-    if ((st = dalloc(c, &sn, (size_t)S * m)) != HH_OK) break;
-    if ((st = dalloc(c, &g, (size_t)S * (m + 1))) != HH_OK) break;
-    if ((st = dalloc(c, &h1, (size_t)S * (m + 2))) != HH_OK) break;
-    if ((st = dalloc(c, &need, (size_t)S)) != HH_OK) break;
-    if ((st = dalloc(c, &h2, (size_t)S * (m + 1))) != HH_OK) break;
-    if ((st = dalloc(c, &tmp, (size_t)S * (m + 1))) != HH_OK) break;
-    if ((st = dalloc(c, &y, (size_t)S * m)) != HH_OK) break;
-    if ((st = dalloc(c, &hn, (size_t)S)) != HH_OK) break;
-    if ((st = dalloc(c, &est, (size_t)S)) != HH_OK) break;
-    if ((st = dalloc(c, &thr, (size_t)S)) != HH_OK) break;
-    if ((st = dalloc(c, &state, (size_t)3 * S)) != HH_OK) break;
-    if ((st = dalloc(c, &any, (size_t)2)) != HH_OK) break;
-    if ((st = ensure_partial(c, (size_t)(m + 2) * S * sg.NBmax)) != HH_OK) break;
-    if ((st = ensure_poll(c)) != HH_OK) break;
-  } while (false);
-  if (st != HH_OK) {
-    cleanup();
-    return st;
-  }
-#define GC(expr)                                    \
-  do {                                              \
-    hipError_t e_ = (expr);                         \
-    if (e_ != hipSuccess) {                         \
-      cleanup();                                    \
-      return device_fail(c, #expr, e_);             \
-    }                                               \
-  } while (0)
-#define GT(expr)              \
-  do {                        \
-    hh_status s2_ = (expr);   \
-    if (s2_ != HH_OK) {       \
-      cleanup();              \
-      return s2_;             \
-    }                         \
-  } while (0)
+  HH_TRY(ensure_gmres(c, q, m));
+  HH_TRY(ensure_partial(c, (size_t)(m + 2) * S * sg.NBmax));
+  HH_TRY(ensure_poll(c));
+  hh_ctx::Gmres& w = c->gw;
+  c128 *Vb = w.Vb, *Zb = w.Zb, *W = w.W, *H = w.H, *g = w.g, *tmp = w.tmp, *y = w.y;
+  double* thr = w.thr;
+  int* state = w.state;
+#define GC(expr) HH_CHECK(expr)
+#define GT(expr) HH_TRY(expr)
   const long long vs = (long long)q * n;
   std::vector<double> beta(S), th(S);
   std::vector<int> hstate(3 * S);
@@ -1107,29 +1260,9 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
       ~ActiveScope() { c->act = nullptr; }
     } act_scope(c, state);
     for (int j = 0; j < m; ++j) {
-      const c128* vj = Vb + j * vs;
-      c128* zj = Zb + j * vs;
-      GT(two_level(c, 0, q, vj, zj));
-      GC(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, zj, nullptr, W, 0, s, state));
-      // classical Gram-Schmidt twice; the second update also gives ||w||^2
-      // classical Gram-Schmidt; the second pass runs for the columns whose first
-      // pass cancelled by more than the factor reorth_eta (all columns when >= 1)
-      const double vbytes = 16.0 * (double)n * q;
-      {
-        ProfScope ps(c, 2, vbytes * (j + 1 + (j + 8) / 8), 8.0 * n * q * (j + 1));
-        GC(launch_multidot(j + 1, sg, Vb, vs, W, c->d_partial, h1, s, 1, state));
-      }
-      {
-        ProfScope ps(c, 1, vbytes * (j + 3), 8.0 * n * q * (j + 1));
-        GC(launch_basis_update(j + 1, sg, Vb, vs, h1, W, c->d_partial, tmp, s, state));
-      }
-      GC(launch_reorth_flag(S, j + 1, h1 + (size_t)(j + 1) * S, tmp, c->reorth_eta, need, h2, s, state));
-      GC(launch_multidot(j + 1, sg, Vb, vs, W, c->d_partial, h2, s, 0, need));
-      GC(launch_basis_update(j + 1, sg, Vb, vs, h2, W, c->d_partial, tmp, s, need));
-      GC(launch_normalize(sg, tmp, W, Vb + (j + 1) * vs, hn, s, state));
-      GC(launch_gmres_step(S, j, m, H, h1, h2, hn, cs, sn, g, est, state, thr, maxit, any, s));
+      GT(run_step(c, q, j, maxit));
       // poll the active count one step late so the stream never drains
-      GC(hipMemcpyAsync(poll + (j & 1), any, sizeof(int), hipMemcpyDeviceToHost, s));
+      GC(hipMemcpyAsync(poll + (j & 1), w.any, sizeof(int), hipMemcpyDeviceToHost, s));
       GC(hipEventRecord(c->poll_ev[j & 1], s));
       if (j > 0) {
         GC(hipEventSynchronize(c->poll_ev[(j - 1) & 1]));
@@ -1144,7 +1277,7 @@ hh_status gmres(hh_ctx* c, int q, const c128* b, c128* u, double rtol, int maxit
     GC(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, u, b, W, 1, s));
     GT(norms(c, W, tmp, beta));
   }
-  cleanup();
+  w.solves += 1;
 #undef GC
 #undef GT
   return HH_OK;
@@ -1331,6 +1464,8 @@ hh_status set_stream(hh_ctx* c, hipStream_t s) {
 
 void release_work(hh_ctx* c) {
   if (!c) return;
+  release_gmres(c);
+  ++c->epoch;
   for (Level& L : c->lv) {
     for (c128** b : {&L.R, &L.X, &L.T, &L.E, &L.U, &L.cvec, &L.yvec, &L.W, &L.RP}) {
       dfree(c, *b);
