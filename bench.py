@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=512,
                     help="independent problems of the batched measurement (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed steps of the batched measurement")
+    ap.add_argument("--no-steady", action="store_true", help="skip the steady-state (cached setup) solve measurement")
     return ap.parse_args()
 
 
@@ -378,6 +379,34 @@ def batched(hh, torch, precision, count, steps, warmup=1, seed=4):
     }
 
 
+def steady_state(hh, torch, precision, N, k, m, rank, nrhs, graphs, solves=6, seed=21):
+    """Repeated solves on one prepared context (setup and coarse space cached): solves/s over the
+    last solves-2 (the first runs eagerly and tunes the sweep, the second captures the step graphs)."""
+    import workloads as W
+
+    stream = torch.cuda.Stream()
+    ctx = hh.hh_setup(2, N, k, hh.decomposition(m, [4]), precision=precision, outer=hh.HH_GMRES, gmres_restart=50,
+                      stream=stream, autotune=True, graphs=graphs)
+    m_in, _, s = hh.hh_level_info(ctx, 1, rank, 10)
+    om = torch.from_numpy(np.concatenate([W.omega_block(0, 1, i, int(m_in[i]), int(s[i])).reshape(-1)
+                                          for i in range(len(m_in))])).to("cuda")
+    torch.cuda.synchronize()
+    hh.hh_build_coarse(ctx, 1, rank, 10, om)
+    f = torch.from_numpy(W.smoothed_gaussian_rhs(N, seed, nrhs)).to("cuda")
+    u = torch.zeros_like(f)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(solves):
+        t0 = time.perf_counter()
+        hh.hh_solve(ctx, f, u, 1e-8, 300, raise_on_notconv=True)
+        times.append(time.perf_counter() - t0)
+    plan = hh.hh_sweep_plan(ctx)
+    hh.hh_destroy(ctx)
+    t = float(np.mean(times[2:]))
+    return {"solves_per_s": round(nrhs / t, 2), "ms_per_solve_call": round(1000 * t, 3),
+            "sweep_qb": [p["qb"] for p in plan]}
+
+
 def copy_calibration(torch):
     n = 1 << 26  # 1 GiB of complex128
     x = torch.ones(n, dtype=torch.complex128, device="cuda")
@@ -456,6 +485,17 @@ def main():
                       "latency = arrival to result on the host",
             "fp64": serving(hh, torch, hh.HH_FP64, args.serving_seconds, args.serving_rate, args.serving_drain),
             "mixed": serving(hh, torch, hh.HH_MIXED, args.serving_seconds, args.serving_rate, args.serving_drain),
+        }
+    if not args.no_steady:
+        prec = hh.HH_MIXED if args.precision == "mixed" else hh.HH_FP64
+        out["steady_state"] = {
+            "note": "repeated hh_solve on one prepared context (setup + coarse space cached), autotuned sweep; "
+                    "eager steps vs captured HIP-graph steps",
+            "helm2d_n256_k40_4x4_64rhs": {g: steady_state(hh, torch, prec, CFG["N"], CFG["k"], CFG["m"], CFG["rank"],
+                                                          args.nrhs, g == "graphs")
+                                          for g in ("eager", "graphs")},
+            "helm2d_n128_k20_2x2_1rhs": {g: steady_state(hh, torch, prec, 128, 20.0, [(2, 2)], 8, 1, g == "graphs")
+                                         for g in ("eager", "graphs")},
         }
     if args.batch_count > 0:
         out["batched"] = {
