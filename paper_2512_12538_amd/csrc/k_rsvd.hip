@@ -12,6 +12,7 @@
 namespace {
 
 constexpr int TB = 256;
+constexpr int TBS = 1024;  // the small dense factorisations: one item (column, column pair) per wave
 constexpr int WAVE = 64;
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -115,7 +116,7 @@ __global__ void __launch_bounds__(TB) k_trace_adjoint(const OpDev* __restrict__ 
 
 // Batched Householder QR, one work-group per problem.  On exit A holds the
 // explicit thin Q (columns >= min(m, n) are zero) and R the n x n upper factor.
-__global__ void __launch_bounds__(TB) k_qr(const int* __restrict__ ms, const int* __restrict__ ns,
+__global__ void __launch_bounds__(TBS) k_qr(const int* __restrict__ ms, const int* __restrict__ ns,
                                            const long long* __restrict__ aoff, c128* __restrict__ Aall,
                                            const long long* __restrict__ roff, c128* __restrict__ Rall,
                                            c128* __restrict__ Wall) {
@@ -124,11 +125,11 @@ __global__ void __launch_bounds__(TB) k_qr(const int* __restrict__ ms, const int
   c128* A = Aall + aoff[pb];
   c128* Vr = Wall + aoff[pb];  // reflectors, same shape as A
   c128* R = Rall + roff[pb];
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE, nw = TB / WAVE;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE, nw = TBS / WAVE;
   __shared__ double s_tau[128];
   __shared__ double2 s_alpha;
   const int kq = m < n ? m : n;
-  for (int e = tid; e < n * n; e += TB) R[e] = mk(0.0, 0.0);
+  for (int e = tid; e < n * n; e += TBS) R[e] = mk(0.0, 0.0);
   for (int k = 0; k < kq; ++k) {
     if (wv == 0) {
       double nrm2 = 0.0;
@@ -166,11 +167,11 @@ __global__ void __launch_bounds__(TB) k_qr(const int* __restrict__ ms, const int
       }
     }
     __syncthreads();
-    for (int c = k + 1 + tid; c < n; c += TB) R[k + (long long)c * n] = A[k + (long long)c * m];
+    for (int c = k + 1 + tid; c < n; c += TBS) R[k + (long long)c * n] = A[k + (long long)c * m];
     __syncthreads();
   }
   // explicit Q = H_0 H_1 ... H_{kq-1} [I; 0]
-  for (int e = tid; e < m * n; e += TB) {
+  for (int e = tid; e < m * n; e += TBS) {
     const int i = e % m, c = e / m;
     A[e] = (i == c && c < kq) ? mk(1.0, 0.0) : mk(0.0, 0.0);
   }
@@ -194,7 +195,7 @@ __global__ void __launch_bounds__(TB) k_qr(const int* __restrict__ ms, const int
 // One-sided (Hestenes) Jacobi on the columns of R (n x n), round-robin pair
 // order, one wave per pair.  Output: U[:, t] = columns of R J normalised and
 // sorted by decreasing norm (the left singular vectors of R), sigma sorted.
-__global__ void __launch_bounds__(TB) k_jacobi(const int* __restrict__ ns, const long long* __restrict__ roff,
+__global__ void __launch_bounds__(TBS) k_jacobi(const int* __restrict__ ns, const long long* __restrict__ roff,
                                                c128* __restrict__ Rall, const long long* __restrict__ uoff,
                                                c128* __restrict__ Uall, double* __restrict__ sig,
                                                const long long* __restrict__ soff) {
@@ -203,7 +204,7 @@ __global__ void __launch_bounds__(TB) k_jacobi(const int* __restrict__ ns, const
   c128* R = Rall + roff[pb];
   c128* U = Uall + uoff[pb];
   double* sg = sig + soff[pb];
-  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE, nw = TB / WAVE;
+  const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE, nw = TBS / WAVE;
   __shared__ int s_rot;
   __shared__ double s_norm[128];
   __shared__ int s_ord[128];
@@ -268,13 +269,13 @@ __global__ void __launch_bounds__(TB) k_jacobi(const int* __restrict__ ns, const
     }
   }
   __syncthreads();
-  for (int e = tid; e < n * n; e += TB) {
+  for (int e = tid; e < n * n; e += TBS) {
     const int i = e % n, c = e / n;
     const int src = s_ord[c];
     const double nv = s_norm[src];
     U[e] = nv > 0.0 ? cscale(R[i + (long long)src * n], 1.0 / nv) : mk(0.0, 0.0);
   }
-  for (int c = tid; c < n; c += TB) sg[c] = s_norm[s_ord[c]];
+  for (int c = tid; c < n; c += TBS) sg[c] = s_norm[s_ord[c]];
 }
 
 __global__ void __launch_bounds__(TB) k_small_gemm(const int* __restrict__ ms, const int* __restrict__ ns,
@@ -348,14 +349,14 @@ hipError_t launch_trace_adjoint(const OpDev* ops, const BoxDev* boxes, int nbox,
 hipError_t launch_qr(int nprob, const int* m, const int* n, const long long* aoff, c128* A, const long long* roff,
                      c128* R, c128* work, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_qr, dim3(nprob), dim3(TB), 0, s, m, n, aoff, A, roff, R, work);
+  hipLaunchKernelGGL(k_qr, dim3(nprob), dim3(TBS), 0, s, m, n, aoff, A, roff, R, work);
   return hipGetLastError();
 }
 
 hipError_t launch_jacobi_svd(int nprob, const int* n, const long long* roff, c128* R, const long long* uoff,
                              c128* U, double* sigma, const long long* soff, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_jacobi, dim3(nprob), dim3(TB), 0, s, n, roff, R, uoff, U, sigma, soff);
+  hipLaunchKernelGGL(k_jacobi, dim3(nprob), dim3(TBS), 0, s, n, roff, R, uoff, U, sigma, soff);
   return hipGetLastError();
 }
 
