@@ -54,6 +54,12 @@ from .geometry import Box, Hierarchy, build_hierarchy, owned_mask, parent_local_
 from .operator import box_matrix, global_matrix
 
 
+# A coarse mode of box i whose extension P_i S_i(B_i^T v) has a norm on the owned
+# nodes of at most NEGLIGIBLE times the largest of the box's modes is not used: it
+# adds a (numerically) zero column to C and makes A_c singular.
+NEGLIGIBLE = 1e-10
+
+
 @dataclass
 class Coarse:
     """Coarse space of one parent problem: blocks C_i on the owned nodes of each child."""
@@ -298,6 +304,10 @@ class HierarchicalORAS:
                 else:
                     V, sig = np.zeros((self.H.levels[lvl][c].interface.size, 0), dtype=np.complex128), np.zeros(0)
                 Ci = self.extend(lvl, c, V) if V.shape[1] else np.zeros((int(self.own[lvl][c].sum()), 0), np.complex128)
+                if Ci.shape[1]:
+                    norms = np.linalg.norm(Ci, axis=0)
+                    keep = norms > NEGLIGIBLE * norms.max()
+                    Ci, V = Ci[:, keep], V[:, keep]
                 own_idx.append(self.R[lvl][c][self.own[lvl][c]])
                 blocks.append(Ci)
                 Vs.append(V)

@@ -22,6 +22,11 @@
 
 namespace {
 
+// A coarse mode whose extension P_i S_i(B_i^T v) has a norm on the owned nodes of at
+// most this fraction of the largest of its box is not used (it would add a
+// numerically zero column to C and make A_c singular).
+constexpr double kNegligibleMode = 1e-10;
+
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
@@ -964,9 +969,10 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
             *d_sgoff = nullptr;
   c128 *Y = nullptr, *Wk = nullptr, *Rs = nullptr, *Us = nullptr, *BH = nullptr, *V = nullptr;
   double* d_sig = nullptr;
+  int* d_drop = nullptr;
   auto cleanup = [&]() {
     for (void* p : std::initializer_list<void*>{d_qm, d_qn, d_bm, d_rr, d_yoff, d_soff, d_bhoff, d_voff, d_omoff,
-                                                d_sgoff, Y, Wk, Rs, Us, BH, V, d_sig})
+                                                d_sgoff, Y, Wk, Rs, Us, BH, V, d_sig, d_drop})
       dfree(c, p);
   };
   hh_status st = HH_OK;
@@ -989,6 +995,7 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
     if ((st = dalloc(c, &BH, (size_t)std::max<long long>(bht, 1))) != HH_OK) break;
     if ((st = dalloc(c, &V, (size_t)std::max<long long>(vt, 1))) != HH_OK) break;
     if ((st = dalloc(c, &d_sig, (size_t)Lv.nbox * smax)) != HH_OK) break;
+    if ((st = dalloc(c, &d_drop, (size_t)Lv.nbox * rmax)) != HH_OK) break;
   } while (false);
   if (st != HH_OK) {
     cleanup();
@@ -1038,10 +1045,13 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   BC(launch_iface_scatter(Lv.d, Lv.nbox, rmax, Lv.d_if, d_voff, V, 1, Lv.R, s));
   BT(solve_level(c, level, rmax, Lv.R, Lv.X));
   BC(launch_extract_owned(Lv.d, Lv.nbox, Lv.max_own, rmax, Lv.X, Lv.C, s));
+  // modes whose extension is (numerically) zero on the owned nodes are dropped
+  BC(launch_drop_negligible(Lv.d, Lv.nbox, rmax, kNegligibleMode, Lv.C, d_drop, s));
   // A_c = C^H A_P C, then its inverse
   BC(launch_galerkin_ac(c->d_ops, Lv.d, Lv.nbox, P.d, Lv.d_dil, max_dil, rmax, Lv.C, Lv.AC, s));
   BC(launch_fill_zero(P.Ainv, nc2 * sizeof(c128), s));
   BC(launch_galerkin_blocks(Lv.d, P.dp, Lv.d_pairs, Lv.npairs, rmax, Lv.d_dil, Lv.C, Lv.AC, P.Ainv, s));
+  BC(launch_unit_dropped(Lv.d, P.dp, Lv.nbox, rmax, d_drop, P.Ainv, s));
   BC(launch_copy(P.Ainv, P.Araw, nc2, s));
   BC(launch_gj_inverse(P.dp, P.nbox, max_nc, P.Ainv, P.d_piv, Wk, c->d_info, s));
   std::vector<int> info(P.nbox);

@@ -90,6 +90,55 @@ __global__ void __launch_bounds__(TB) k_galerkin_blocks(const BoxDev* __restrict
   }
 }
 
+// A mode t of box i whose column of C_i has a norm of at most tol times the
+// box's largest column norm is dropped: the column is zeroed (so A_c gets a zero
+// row and column there) and drop[i * rmax + t] = 1.  One work-group per box,
+// one wave per column.
+constexpr int TBD = 1024;
+__global__ void __launch_bounds__(TBD) k_drop_negligible(const BoxDev* __restrict__ boxes, int rmax, double tol,
+                                                         c128* __restrict__ C, int* __restrict__ drop) {
+  const BoxDev B = boxes[blockIdx.x];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  __shared__ double nrm[128];
+  __shared__ double big;
+  for (int t = threadIdx.x; t < rmax; t += TBD) drop[(long long)blockIdx.x * rmax + t] = 0;
+  if (B.r == 0) return;
+  c128* Cb = C + B.coff;
+  for (int t = wv; t < B.r; t += TBD / 64) {
+    double a = 0.0;
+    for (int e = lane; e < B.n_own; e += 64) a += cabs2(Cb[(long long)t * B.n_own + e]);
+    a = wave_sum(a);
+    if (lane == 0) nrm[t] = sqrt(a);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int t = 0; t < B.r; ++t) mx = fmax(mx, nrm[t]);
+    big = mx;
+  }
+  __syncthreads();
+  const double lim = tol * big;
+  for (int t = wv; t < B.r; t += TBD / 64) {
+    if (nrm[t] > lim) continue;
+    if (lane == 0) drop[(long long)blockIdx.x * rmax + t] = 1;
+    for (int e = lane; e < B.n_own; e += 64) Cb[(long long)t * B.n_own + e] = mk(0.0, 0.0);
+  }
+}
+
+// A_c[cidx + t][cidx + t] = 1 for the dropped modes (their row and column are
+// zero), so the inverse gives them a zero coarse value.
+__global__ void k_unit_dropped(const BoxDev* __restrict__ boxes, const ParentDev* __restrict__ pd, int nbox,
+                               int rmax, const int* __restrict__ drop, c128* __restrict__ A) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nbox * rmax) return;
+  const int box = idx / rmax, t = idx - box * rmax;
+  const BoxDev B = boxes[box];
+  if (t >= B.r || !drop[idx]) return;
+  const ParentDev D = pd[B.parent];
+  const long long d = B.cidx + t;
+  A[D.aoff + d + d * D.n_c] = mk(1.0, 0.0);
+}
+
 // Gauss-Jordan inversion of every parent's A_c spread over the whole GPU: one
 // launch per pivot selects and interchanges the pivot row, scales it and saves
 // the pivot column; a second launch eliminates the column from all other rows
@@ -429,6 +478,21 @@ hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, co
   if (npairs <= 0 || rmax <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_galerkin_blocks, dim3(npairs * rmax), dim3(TB), 0, s, boxes, pars, pairs, rmax, dil, C, AC,
                      Ac);
+  return hipGetLastError();
+}
+
+hipError_t launch_drop_negligible(const BoxDev* boxes, int nbox, int rmax, double tol, c128* C, int* drop,
+                                  hipStream_t s) {
+  if (nbox <= 0 || rmax <= 0) return hipSuccess;
+  if (rmax > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_drop_negligible, dim3(nbox), dim3(TBD), 0, s, boxes, rmax, tol, C, drop);
+  return hipGetLastError();
+}
+
+hipError_t launch_unit_dropped(const BoxDev* boxes, const ParentDev* pd, int nbox, int rmax, const int* drop,
+                               c128* A, hipStream_t s) {
+  if (nbox <= 0 || rmax <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_unit_dropped, dim3((nbox * rmax + 255) / 256), dim3(256), 0, s, boxes, pd, nbox, rmax, drop, A);
   return hipGetLastError();
 }
 

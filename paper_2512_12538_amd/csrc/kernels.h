@@ -90,6 +90,13 @@ hipError_t launch_galerkin_ac(const OpDev* ops, const BoxDev* boxes, int nbox, c
 hipError_t launch_galerkin_blocks(const BoxDev* boxes, const ParentDev* pars, const int4* pairs, int npairs,
                                   int rmax, const int4* dil, const c128* C, const c128* AC, c128* Ac,
                                   hipStream_t s);
+// Negligible coarse modes: a column of C_i whose norm on the owned nodes is at most tol
+// times the box's largest is zeroed and flagged in drop[box * rmax + t] (rmax <= 128)
+hipError_t launch_drop_negligible(const BoxDev* boxes, int nbox, int rmax, double tol, c128* C, int* drop,
+                                  hipStream_t s);
+// A_c diagonal entries of the dropped modes set to one (their rows and columns are zero)
+hipError_t launch_unit_dropped(const BoxDev* boxes, const ParentDev* pd, int nbox, int rmax, const int* drop,
+                               c128* A, hipStream_t s);
 // In-place inverse of every parent's A_c (Gauss-Jordan, partial pivoting); piv and fcol hold
 // npar*max_nc entries; info[p] = first zero pivot + 1 (0 if none)
 hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* A, int* piv, c128* fcol, int* info,

@@ -330,3 +330,56 @@ def test_recreated_context_reuses_cached_memory_with_identical_results(hh):
     assert np.array_equal(outs[0], outs[1])
     assert hh.hh_release_cached_memory() > 0
     assert hh.hh_release_cached_memory() == 0
+
+
+# ---------------------------------------------------------------- limits and degenerate cases
+def test_widest_supported_leaf_and_the_limit(hh):
+    """Leaves 256 nodes wide (the largest sweep shape) match the oracle; 257 is refused."""
+    from gpu_util import build_both, dev, host, rel
+
+    N = 255
+    n = (N + 1) ** 2
+    k = np.random.default_rng(9).uniform(10, 14, n)
+    ctx = hh.hh_setup(2, N, k, hh.decomposition([(2, 1)], [4]))
+    S = HierarchicalORAS(2, N, k, [(2, 1)], [4])
+    try:
+        build_both(hh, ctx, S, rank=0, oversample=0)
+        r = W.white_rhs(n, 14, 2)
+        z = dev(np.zeros_like(r))
+        hh.hh_precondition(ctx, dev(r), z)
+        ref = np.stack([S.precondition(r[i]) for i in range(2)])
+        assert rel(host(z), ref) < 1e-11
+    finally:
+        hh.hh_destroy(ctx)
+    with pytest.raises(hh.HelmddError) as e:
+        hh.hh_setup(2, 256, 12.0, hh.decomposition([(2, 1)], [4]))
+    assert e.value.status == hh.HH_EUNSUPPORTED
+
+
+def test_full_interface_space_is_exact_in_one_step(hh):
+    """Rank above the interface size: r_i = m_in, the coarse space spans every
+    interface mode and one stationary step solves the problem (Sec. 2)."""
+    from gpu_util import build_both, dev, host, rel
+
+    N = 24
+    n = (N + 1) ** 2
+    k = np.full(n, 5.0)
+    ctx = hh.hh_setup(2, N, k, hh.decomposition([(2, 2)], [2]), outer=hh.HH_STATIONARY)
+    S = HierarchicalORAS(2, N, k, [(2, 2)], [2])
+    try:
+        m_in, r, s = hh.hh_level_info(ctx, 1, 1000, 10)
+        assert list(r) == list(m_in) and list(s) == list(m_in)
+        build_both(hh, ctx, S, rank=1000, oversample=10)
+        # some modes extend to nothing on the owned nodes and are dropped on both sides
+        assert S.coarse[0][0].size < int(np.sum(r))
+        f = W.white_rhs(n, 15)
+        z = dev(np.zeros_like(f))
+        hh.hh_precondition(ctx, dev(f), z)
+        assert rel(host(z)[0], S.precondition(f[0])) < 1e-9
+        u = dev(np.zeros_like(f))
+        info = hh.hh_solve(ctx, dev(f), u, rtol=0.0, maxit=1)
+        assert info[0][0] == 1
+        us = op.direct_solve(S.A, f[0])
+        assert rel(host(u)[0], us) < 1e-9
+    finally:
+        hh.hh_destroy(ctx)

@@ -262,3 +262,23 @@ def test_build_order_enforced():
     S = _solver(2, 32, [(2, 2), (2, 2)], [4, 4], k=8.0)
     with pytest.raises(RuntimeError):
         S.build_coarse(1, 2, 2, omegas(S, 1, 2, 2))
+
+
+def test_negligible_modes_are_dropped_and_the_step_stays_exact():
+    # rank above the interface size with a thin overlap: some interface modes extend to
+    # (numerically) nothing on the owned nodes; they are left out of C (A_c stays
+    # invertible) and the full interface space still makes one step exact (Sec. 2).
+    N = 24
+    S = _solver(2, N, [(2, 2)], [2], k=5.0)
+    oms = []
+    for i in range(4):
+        m_in, _, s = S.sizes(1, i, 10**6, 10)
+        oms.append(W.omega_block(0, 1, i, m_in, s))
+    S.build_coarse(1, 10**6, 10, oms)
+    cs = S.coarse[0][0]
+    full = sum(S.sizes(1, i, 10**6, 10)[1] for i in range(4))
+    assert 0 < cs.size < full
+    assert np.linalg.cond(cs.Ac) < 1e12
+    f = W.white_rhs((N + 1) ** 2, 15)[0]
+    u = S.precondition(f)
+    assert np.linalg.norm(f - S.A @ u) / np.linalg.norm(f) < 1e-10
