@@ -409,6 +409,26 @@ def steady_state(hh, torch, precision, N, k, m, rank, nrhs, graphs, solves=6, se
             "sweep_qb": [p["qb"] for p in plan]}
 
 
+def guarded(fn, *a, **kw):
+    """Runs an optional measurement; a failure is recorded in the JSON line instead of ending the run."""
+    try:
+        return fn(*a, **kw)
+    except Exception as e:  # noqa: BLE001 - any failure of a side measurement is reported, not raised
+        print(f"bench: {getattr(fn, '__name__', fn)} failed: {e}", file=sys.stderr, flush=True)
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
+def section_done(torch, name):
+    """Progress line, and a device round trip so that an error left by a section is reported there."""
+    try:
+        torch.cuda.synchronize()
+        torch.ones(1, device="cuda").add_(1)
+        torch.cuda.synchronize()
+        print(f"bench: {name} done", file=sys.stderr, flush=True)
+    except Exception as e:  # noqa: BLE001 - reported; the next measurement records its own failure
+        print(f"bench: device error after {name}: {e}", file=sys.stderr, flush=True)
+
+
 def copy_calibration(torch):
     n = 1 << 26  # 1 GiB of complex128
     x = torch.ones(n, dtype=torch.complex128, device="cuda")
@@ -468,6 +488,7 @@ def main():
         "solve_only_solves_per_s": round(args.nrhs / float(np.mean(res["phases"]["solve"])), 3),
         "roofline": roofline(res["prof"], args.precision, args.nrhs),
     }
+    section_done(torch, "main workload")
     if not args.no_mixed and args.precision == "fp64":
         mres = run_gpu(hh, torch, args.nrhs, hh.HH_MIXED, max(2, args.steps // 2), 1, False)
         mlat = np.array(mres["lat"]) * 1000.0
@@ -479,6 +500,7 @@ def main():
             "solve_only_solves_per_s": round(args.nrhs / float(np.mean(mres["phases"]["solve"])), 3),
             "gmres_iterations_mean": round(float(np.mean(mres["iters"])), 2),
         }
+        section_done(torch, "mixed precision")
     if args.serving_seconds > 0:
         out["serving"] = {
             "stream": f"Poisson arrivals for {args.serving_seconds:g} s (then {args.serving_drain:g} s to drain); "
@@ -487,32 +509,37 @@ def main():
                       "host, requests unfinished at the deadline count as infinitely late",
         }
         for rate in [args.serving_rate] + ([args.serving_rate_low] if args.serving_rate_low > 0 else []):
-            out["serving"][f"rate_{rate:g}_per_s"] = {
-                "fp64": serving(hh, torch, hh.HH_FP64, args.serving_seconds, rate, args.serving_drain),
-                "mixed": serving(hh, torch, hh.HH_MIXED, args.serving_seconds, rate, args.serving_drain),
-            }
+            res = {}
+            for name, prec in (("fp64", hh.HH_FP64), ("mixed", hh.HH_MIXED)):
+                section_done(torch, f"before serving {name} at {rate:g}/s")
+                res[name] = guarded(serving, hh, torch, prec, args.serving_seconds, rate, args.serving_drain)
+            out["serving"][f"rate_{rate:g}_per_s"] = res
+        section_done(torch, "serving")
     if not args.no_steady:
         prec = hh.HH_MIXED if args.precision == "mixed" else hh.HH_FP64
         out["steady_state"] = {
             "note": "repeated hh_solve on one prepared context (setup + coarse space cached), autotuned sweep; "
                     "eager steps vs captured HIP-graph steps",
-            "helm2d_n256_k40_4x4_64rhs": {g: steady_state(hh, torch, prec, CFG["N"], CFG["k"], CFG["m"], CFG["rank"],
-                                                          args.nrhs, g == "graphs")
+            "helm2d_n256_k40_4x4_64rhs": {g: guarded(steady_state, hh, torch, prec, CFG["N"], CFG["k"], CFG["m"],
+                                                                  CFG["rank"], args.nrhs, g == "graphs")
                                           for g in ("eager", "graphs")},
-            "helm2d_n128_k20_2x2_1rhs": {g: steady_state(hh, torch, prec, 128, 20.0, [(2, 2)], 8, 1, g == "graphs")
+            "helm2d_n128_k20_2x2_1rhs": {g: guarded(steady_state, hh, torch, prec, 128, 20.0, [(2, 2)], 8, 1,
+                                                    g == "graphs")
                                          for g in ("eager", "graphs")},
         }
+        section_done(torch, "steady state")
     if args.batch_count > 0:
+        hh.hh_release_cached_memory()  # the serving runs leave the device cache full
         out["batched"] = {
             "workload": f"helm2d_batch{args.batch_count}: {args.batch_count} independent problems, side uniform in "
                         "{64,96,128,192,256}, k = side/6.4, m x m boxes with m uniform in {2,3,4}, 4-cell overlap, "
                         "rank 8 per interface + 10, one white Gaussian RHS each, GMRES(50) to 1e-8; one context, "
                         "every level of every problem in the same launches; step = setup + coarse build + solve",
-            "mixed": batched(hh, torch, hh.HH_MIXED, args.batch_count, args.batch_steps),
-            "fp64": batched(hh, torch, hh.HH_FP64, args.batch_count, args.batch_steps),
+            "mixed": guarded(batched, hh, torch, hh.HH_MIXED, args.batch_count, args.batch_steps),
+            "fp64": guarded(batched, hh, torch, hh.HH_FP64, args.batch_count, args.batch_steps),
         }
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args.cpu_rhs)
+        out["cpu_baseline"] = guarded(cpu_baseline, args.cpu_rhs)
     print(json.dumps(out), flush=True)
 
 

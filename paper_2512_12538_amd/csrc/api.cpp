@@ -553,6 +553,7 @@ hh_status hh_destroy(hh_ctx* c) {
   for (const DevBuf& b : c->allocs) devpool::release(b.p, b.bytes, c->stream);
   c->allocs.clear();
   delete c;
+  (void)hipGetLastError();  // clean-up ignores errors; leave none behind for the caller's next call
   return HH_OK;
 }
 

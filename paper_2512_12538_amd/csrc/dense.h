@@ -3,67 +3,72 @@
 
 #include "common.h"
 
-// In-place inverse of the n x n column-major complex matrix A by Gauss-Jordan
-// elimination with partial (row) pivoting; row interchanges are undone as
-// column interchanges at the end.  Every thread of the block must call it.
-// Scratch (shared memory): fcol[n], perm[n], rv[NT], ri[NT].  On a zero pivot
-// *flag (shared) is set to (step + 1) and the elimination continues with a
-// zero reciprocal, so the caller can report a singular matrix.
+// In-place inverse of the n x n column-major complex matrix A (n <= 256) by
+// Gauss-Jordan elimination with partial (row) pivoting; row interchanges are
+// undone as column interchanges at the end.  Every thread of the block must
+// call it.  A pivot step is three barriers: the first wave finds the pivot
+// (largest modulus at or below the diagonal, first on ties) with shuffles;
+// every thread then stages the new pivot row, the old row kk and the
+// multipliers in shared memory from the values before the step; finally every
+// element is updated from the staged values, the interchange folded in.
+// Scratch (shared memory): rowk[n], rold[n], fcol[n], perm[n].  On a zero pivot
+// *flag (shared) is set to (step + 1) and the elimination continues with a zero
+// reciprocal, so the caller can report a singular matrix.
 template <int NT>
-__device__ void gj_inverse_inplace(double2* A, int n, double2* fcol, int* perm, double* rv, int* ri,
-                                   double2* s_inv, int* flag) {
+__device__ void gj_inverse_inplace(double2* A, int n, double2* rowk, double2* rold, double2* fcol, int* perm,
+                                   int* s_piv, int* flag) {
   const int tid = threadIdx.x;
+  // element (i, c) of this thread's first slot and the stride between slots
+  const int i0 = tid % n, c0 = tid / n, di = NT % n, dc = NT / n;
   for (int kk = 0; kk < n; ++kk) {
-    double best = -1.0;
-    int bi = kk;
-    for (int i = kk + tid; i < n; i += NT) {
-      const double a = cabs2(A[i + (long long)kk * n]);
-      if (a > best) { best = a; bi = i; }
-    }
-    rv[tid] = best;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int st = NT / 2; st > 0; st >>= 1) {
-      if (tid < st) {
-        const double o = rv[tid + st];
-        const int oi = ri[tid + st];
-        if (o > rv[tid] || (o == rv[tid] && oi < ri[tid])) { rv[tid] = o; ri[tid] = oi; }
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = kk;
+      for (int i = kk + tid; i < n; i += 64) {
+        const double a = cabs2(A[i + (long long)kk * n]);
+        if (a > best) { best = a; bi = i; }
       }
-      __syncthreads();
-    }
-    const int pr = ri[0];
-    if (tid == 0) perm[kk] = pr;
-    if (pr != kk) {
-      for (int c = tid; c < n; c += NT) {
-        const double2 t = A[kk + (long long)c * n];
-        A[kk + (long long)c * n] = A[pr + (long long)c * n];
-        A[pr + (long long)c * n] = t;
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        *s_piv = bi;
+        perm[kk] = bi;
       }
     }
     __syncthreads();
-    if (tid == 0) {
-      const double2 pv = A[kk + (long long)kk * n];
-      if (cabs2(pv) == 0.0) {
-        if (*flag == 0) *flag = kk + 1;
-        *s_inv = mk(0.0, 0.0);
-      } else {
-        *s_inv = cdiv(mk(1.0, 0.0), pv);
-      }
-    }
-    __syncthreads();
-    const double2 inv = *s_inv;
+    const int p = *s_piv;
+    const double2 pv = A[p + (long long)kk * n];
+    const bool zero = cabs2(pv) == 0.0;
+    if (tid == 0 && zero && *flag == 0) *flag = kk + 1;
+    const double2 inv = zero ? mk(0.0, 0.0) : cdiv(mk(1.0, 0.0), pv);
     for (int c = tid; c < n; c += NT) {
-      const long long e = kk + (long long)c * n;
-      A[e] = (c == kk) ? inv : cmul(A[e], inv);
+      const double2 rk = A[kk + (long long)c * n], rp = A[p + (long long)c * n];
+      rold[c] = rk;
+      rowk[c] = (c == kk) ? inv : cmul(rp, inv);
     }
-    for (int i = tid; i < n; i += NT) fcol[i] = (i == kk) ? mk(0.0, 0.0) : A[i + (long long)kk * n];
+    for (int i = tid; i < n; i += NT) {
+      const double2 v = (i == p) ? A[kk + (long long)kk * n] : A[i + (long long)kk * n];
+      fcol[i] = (i == kk) ? mk(0.0, 0.0) : v;
+    }
     __syncthreads();
-    for (long long e = tid; e < (long long)n * n; e += NT) {
-      const int i = (int)(e % n), c = (int)(e / n);
-      if (i == kk) continue;
-      const double2 rowk = A[kk + (long long)c * n];
-      const double2 base = (c == kk) ? mk(0.0, 0.0) : A[e];
-      A[e] = csub(base, cmul(fcol[i], rowk));
+    int i = i0, c = c0;
+    while (c < n) {
+      const long long e = i + (long long)c * n;
+      if (i == kk) {
+        A[e] = rowk[c];
+      } else {
+        const double2 base = (c == kk) ? mk(0.0, 0.0) : (i == p ? rold[c] : A[e]);
+        A[e] = csub(base, cmul(fcol[i], rowk[c]));
+      }
+      i += di;
+      c += dc;
+      if (i >= n) {
+        i -= n;
+        c += 1;
+      }
     }
     __syncthreads();
   }

@@ -18,8 +18,6 @@
 
 namespace {
 
-constexpr int TB = 256;
-
 __device__ __forceinline__ double2 diag_block(const OpDev& op, const BoxDev& B, int j, int i, int k) {
   const int p = B.p0 + j, q = B.q0 + i;
   if (i == k) return stencil_coef(op, B.p0, B.p1, B.q0, B.q1, p, q, 0, 0);
@@ -70,31 +68,35 @@ __device__ __forceinline__ int eliminated(const BoxDev& B, int mode, int s, int 
 
 // Global-memory variant for wide boxes: S_j is formed in place of G_j and
 // inverted by the work-group with Gauss-Jordan elimination and partial
-// pivoting.
-__global__ void __launch_bounds__(TB) k_leaf_factor(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves,
-                                                    const int* __restrict__ lidx, int mode,
-                                                    c128* __restrict__ G, int* __restrict__ info) {
+// pivoting (1024 threads; the matrix stays in the cache hierarchy).
+constexpr int TBF = 1024;
+__global__ void __launch_bounds__(TBF) k_leaf_factor(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves,
+                                                     const int* __restrict__ lidx, int mode,
+                                                     c128* __restrict__ G, int* __restrict__ info) {
   const LinePlan P = line_plan(leaves, lidx, mode);
   const BoxDev B = leaves[P.leaf];
   const OpDev op = ops[B.prob];
   const int b = B.ny;
   const int tid = threadIdx.x;
   extern __shared__ unsigned char smem_raw[];
-  double2* fcol = reinterpret_cast<double2*>(smem_raw);           // b
-  double* rv = reinterpret_cast<double*>(fcol + b);                // TB
-  int* ri = reinterpret_cast<int*>(rv + TB);                        // TB
-  int* perm = ri + TB;                                              // b
-  __shared__ double2 s_inv;
+  double2* rowk = reinterpret_cast<double2*>(smem_raw);  // b
+  double2* rold = rowk + b;                              // b
+  double2* fcol = rold + b;                              // b
+  int* perm = reinterpret_cast<int*>(fcol + b);          // b
+  __shared__ int s_piv;
   __shared__ int s_flag;
   if (tid == 0) s_flag = 0;
   int first = 0;
+  // element (i, k) of this thread's first slot and the stride between slots
+  const int i0 = tid % b, k0 = tid / b, di = TBF % b, dk = TBF / b;
   for (int s = 0; s < P.count; ++s) {
     const int j = P.first + P.step * s;
     c128* Gj = G + B.goff + (long long)j * b * b;
     int nb[2];
     const int nnb = eliminated(B, mode, s, j, P.step, nb);
-    for (int e = tid; e < b * b; e += TB) {
-      const int i = e % b, k = e / b;
+    int i = i0, k = k0;
+    while (k < b) {
+      const long long e = i + (long long)k * b;
       double2 v = diag_block(op, B, j, i, k);
       for (int t = 0; t < nnb; ++t) {
         const c128* Gp = G + B.goff + (long long)nb[t] * b * b;
@@ -103,10 +105,16 @@ __global__ void __launch_bounds__(TB) k_leaf_factor(const OpDev* __restrict__ op
         v = csub(v, cmul(cmul(ai, Gp[e]), ak));
       }
       Gj[e] = v;
+      i += di;
+      k += dk;
+      if (i >= b) {
+        i -= b;
+        k += 1;
+      }
     }
     __syncthreads();
     const int flag_before = s_flag;
-    gj_inverse_inplace<TB>(Gj, b, fcol, perm, rv, ri, &s_inv, &s_flag);
+    gj_inverse_inplace<TBF>(Gj, b, rowk, rold, fcol, perm, &s_piv, &s_flag);
     if (tid == 0 && first == 0 && flag_before == 0 && s_flag != 0) first = j * b + s_flag;
     __syncthreads();
   }
@@ -216,11 +224,12 @@ hipError_t launch_leaf_factor(const OpDev* ops, const BoxDev* leaves, int nleaf,
     case 2: return launch_reg<512, 12>(ops, leaves, nleaf, lidx, count, G, info, s);
     default: break;
   }
-  const size_t shm = sizeof(double2) * max_ny + (sizeof(double) + sizeof(int)) * TB + sizeof(int) * max_ny;
-  hipLaunchKernelGGL(k_leaf_factor, dim3(2 * count), dim3(TB), shm, s, ops, leaves, lidx, 0, G, info);
+  if (max_ny > 256) return hipErrorInvalidValue;
+  const size_t shm = 3 * sizeof(double2) * max_ny + sizeof(int) * max_ny;
+  hipLaunchKernelGGL(k_leaf_factor, dim3(2 * count), dim3(TBF), shm, s, ops, leaves, lidx, 0, G, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_leaf_factor, dim3(count), dim3(TB), shm, s, ops, leaves, lidx, 1, G,
+  hipLaunchKernelGGL(k_leaf_factor, dim3(count), dim3(TBF), shm, s, ops, leaves, lidx, 1, G,
                      info ? info + 2 * nleaf : nullptr);
   return hipGetLastError();
 }

@@ -461,6 +461,7 @@ hh_status hh_server_destroy(hh_server* sv) {
     if (kv.second.ctx) hh_destroy(kv.second.ctx);
   for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
   delete sv;
+  (void)hipGetLastError();  // clean-up ignores errors; leave none behind for the caller's next call
   return HH_OK;
 }
 
