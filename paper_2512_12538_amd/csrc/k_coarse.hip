@@ -211,6 +211,118 @@ __global__ void __launch_bounds__(TB) k_gj_elim(const ParentDev* __restrict__ pa
   }
 }
 
+// ---- blocked Gauss-Jordan: panels of GJ_NB pivots.  k_gj_panel runs the
+// panel's steps (partial pivoting, the same step as above) on the n x nb panel
+// in shared memory, one work-group per parent, and writes the panel back (its
+// columns then hold the panel's elimination matrix E restricted to them) with
+// the panel's row permutation sig (new row i = old row sig[i]).  k_gj_trail
+// applies the panel to every other column x: x <- S x + (E[:, K] - I[:, K]) (S x)_K,
+// one work-group per (parent, column), the column staged in shared memory.
+constexpr int GJ_NB = 16;
+constexpr int GJ_MAXN = 512;
+
+__global__ void __launch_bounds__(1024) k_gj_panel(const ParentDev* __restrict__ pars, c128* __restrict__ Aall,
+                                                   int* __restrict__ perm_all, int* __restrict__ sig_all, int max_nc,
+                                                   int k0, int* __restrict__ info) {
+  const ParentDev P = pars[blockIdx.x];
+  const int n = P.n_c;
+  if (k0 >= n) return;
+  const int kb = n - k0 < GJ_NB ? n - k0 : GJ_NB;
+  c128* A = Aall + P.aoff;
+  int* perm = perm_all + (long long)blockIdx.x * max_nc;
+  int* sig = sig_all + (long long)blockIdx.x * max_nc;
+  extern __shared__ double2 pan[];  // pan[t * n + i], t < kb
+  double2* fcol = pan + (long long)GJ_NB * n;
+  __shared__ int s_p;
+  __shared__ double2 s_inv;
+  const int tid = threadIdx.x, NT = blockDim.x;
+  for (int e = tid; e < kb * n; e += NT) pan[e] = A[(e % n) + (long long)(k0 + e / n) * n];
+  for (int i = tid; i < n; i += NT) sig[i] = i;
+  __syncthreads();
+  for (int t = 0; t < kb; ++t) {
+    const int kk = k0 + t;
+    double2* col = pan + (long long)t * n;
+    if (tid < 64) {
+      double best = -1.0;
+      int bi = kk;
+      for (int i = kk + tid; i < n; i += 64) {
+        const double a = cabs2(col[i]);
+        if (a > best) { best = a; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (tid == 0) {
+        s_p = bi;
+        perm[kk] = bi;
+        if (best <= 0.0 && info[blockIdx.x] == 0) info[blockIdx.x] = kk + 1;
+        const int tmp = sig[kk];
+        sig[kk] = sig[bi];
+        sig[bi] = tmp;
+      }
+    }
+    __syncthreads();
+    const int pr = s_p;
+    if (pr != kk)
+      for (int c = tid; c < kb; c += NT) {
+        const double2 x = pan[(long long)c * n + kk];
+        pan[(long long)c * n + kk] = pan[(long long)c * n + pr];
+        pan[(long long)c * n + pr] = x;
+      }
+    __syncthreads();
+    if (tid == 0) {
+      const double2 pv = col[kk];
+      s_inv = cabs2(pv) > 0.0 ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+    }
+    __syncthreads();
+    const double2 inv = s_inv;
+    for (int i = tid; i < n; i += NT) fcol[i] = (i == kk) ? mk(0.0, 0.0) : col[i];
+    __syncthreads();
+    for (int c = tid; c < kb; c += NT) {
+      double2& x = pan[(long long)c * n + kk];
+      x = (c == t) ? inv : cmul(x, inv);
+    }
+    __syncthreads();
+    for (int e = tid; e < kb * n; e += NT) {
+      const int i = e % n, c = e / n;
+      if (i == kk) continue;
+      const double2 base = (c == t) ? mk(0.0, 0.0) : pan[e];
+      pan[e] = csub(base, cmul(fcol[i], pan[(long long)c * n + kk]));
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < kb * n; e += NT) A[(e % n) + (long long)(k0 + e / n) * n] = pan[e];
+}
+
+__global__ void __launch_bounds__(256) k_gj_trail(const ParentDev* __restrict__ pars, c128* __restrict__ Aall,
+                                                  const int* __restrict__ sig_all, int max_nc, int k0) {
+  const ParentDev P = pars[blockIdx.y];
+  const int n = P.n_c, c = blockIdx.x;
+  if (k0 >= n || c >= n) return;
+  const int kb = n - k0 < GJ_NB ? n - k0 : GJ_NB;
+  if (c >= k0 && c < k0 + kb) return;
+  c128* A = Aall + P.aoff;
+  const int* sig = sig_all + (long long)blockIdx.y * max_nc;
+  __shared__ double2 xs[GJ_MAXN];
+  __shared__ double2 xk[GJ_NB];
+  c128* xc = A + (long long)c * n;
+  for (int i = threadIdx.x; i < n; i += 256) xs[i] = xc[sig[i]];
+  __syncthreads();
+  if (threadIdx.x < kb) xk[threadIdx.x] = xs[k0 + threadIdx.x];
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double2 v = xs[i];
+    for (int t = 0; t < kb; ++t) {
+      double2 w = A[i + (long long)(k0 + t) * n];
+      if (i == k0 + t) w = csub(w, mk(1.0, 0.0));
+      v = cfma(w, xk[t], v);
+    }
+    xc[i] = v;
+  }
+}
+
 // undo the row interchanges as column interchanges (last first), one row per thread
 __global__ void __launch_bounds__(TB) k_gj_unperm(const ParentDev* __restrict__ pars, c128* __restrict__ Aall,
                                                   const int* __restrict__ perm_all, int max_nc) {
@@ -501,6 +613,19 @@ hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* 
   if (npar <= 0 || max_nc <= 0) return hipSuccess;
   hipError_t e = launch_fill_zero(info, (long long)sizeof(int) * npar, s);
   if (e != hipSuccess) return e;
+  const size_t shm = sizeof(double2) * (size_t)(GJ_NB + 1) * max_nc;
+  if (max_nc <= GJ_MAXN &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(k_gj_panel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)shm) == hipSuccess) {
+    // blocked: two launches per panel of GJ_NB pivots (fcol holds the permutations)
+    int* sig = reinterpret_cast<int*>(fcol);
+    for (int k0 = 0; k0 < max_nc; k0 += GJ_NB) {
+      hipLaunchKernelGGL(k_gj_panel, dim3(npar), dim3(1024), shm, s, pars, A, piv, sig, max_nc, k0, info);
+      hipLaunchKernelGGL(k_gj_trail, dim3(max_nc, npar), dim3(256), 0, s, pars, A, sig, max_nc, k0);
+    }
+    hipLaunchKernelGGL(k_gj_unperm, dim3((max_nc + TB - 1) / TB, npar), dim3(TB), 0, s, pars, A, piv, max_nc);
+    return hipGetLastError();
+  }
   // blocks per parent: enough for one large A_c, few when there are many parents
   // (the elimination loop strides over the matrix)
   const long long nn = (long long)max_nc * max_nc;
@@ -568,6 +693,13 @@ hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ng
   if (ngroups <= 0 || q <= 0) return hipSuccess;
   if (rmax > PR_MAXR) return hipErrorInvalidValue;
   const size_t shm = sizeof(double2) * 64 * (size_t)(rmax + 1);
+  if (shm > 65536) {
+    for (const void* k : {reinterpret_cast<const void*>(k_prolong_mfma<1>), reinterpret_cast<const void*>(k_prolong_mfma<2>),
+                          reinterpret_cast<const void*>(k_prolong_mfma<4>)}) {
+      const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      if (e != hipSuccess) return e;
+    }
+  }
   const dim3 grid(ngroups, (q + 63) / 64);
   if (q <= 16)
     hipLaunchKernelGGL(k_prolong_mfma<1>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u);
