@@ -68,8 +68,11 @@ __device__ __forceinline__ int eliminated(const BoxDev& B, int mode, int s, int 
 
 // Global-memory variant for wide boxes: S_j is formed in place of G_j and
 // inverted by the work-group with Gauss-Jordan elimination and partial
-// pivoting (1024 threads; the matrix stays in the cache hierarchy).
+// pivoting, by panels of FNB pivots held in shared memory (1024 threads).
 constexpr int TBF = 1024;
+constexpr int FNB = 16;
+
+size_t factor_shm(int b) { return sizeof(double2) * (2 * FNB * b + b + FNB) + sizeof(int) * b; }
 __global__ void __launch_bounds__(TBF) k_leaf_factor(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves,
                                                      const int* __restrict__ lidx, int mode,
                                                      c128* __restrict__ G, int* __restrict__ info) {
@@ -79,10 +82,11 @@ __global__ void __launch_bounds__(TBF) k_leaf_factor(const OpDev* __restrict__ o
   const int b = B.ny;
   const int tid = threadIdx.x;
   extern __shared__ unsigned char smem_raw[];
-  double2* rowk = reinterpret_cast<double2*>(smem_raw);  // b
-  double2* rold = rowk + b;                              // b
-  double2* fcol = rold + b;                              // b
-  int* perm = reinterpret_cast<int*>(fcol + b);          // b
+  double2* pan = reinterpret_cast<double2*>(smem_raw);  // FNB b
+  double2* xk = pan + FNB * b;                          // FNB b
+  double2* fcol = xk + FNB * b;                         // b
+  double2* rowk = fcol + b;                             // FNB
+  int* perm = reinterpret_cast<int*>(rowk + FNB);       // b
   __shared__ int s_piv;
   __shared__ int s_flag;
   if (tid == 0) s_flag = 0;
@@ -114,7 +118,7 @@ __global__ void __launch_bounds__(TBF) k_leaf_factor(const OpDev* __restrict__ o
     }
     __syncthreads();
     const int flag_before = s_flag;
-    gj_inverse_inplace<TBF>(Gj, b, rowk, rold, fcol, perm, &s_piv, &s_flag);
+    gj_inverse_blocked<TBF, FNB>(Gj, b, pan, xk, fcol, rowk, perm, &s_piv, &s_flag);
     if (tid == 0 && first == 0 && flag_before == 0 && s_flag != 0) first = j * b + s_flag;
     __syncthreads();
   }
@@ -225,7 +229,12 @@ hipError_t launch_leaf_factor(const OpDev* ops, const BoxDev* leaves, int nleaf,
     default: break;
   }
   if (max_ny > 256) return hipErrorInvalidValue;
-  const size_t shm = 3 * sizeof(double2) * max_ny + sizeof(int) * max_ny;
+  const size_t shm = factor_shm(max_ny);
+  if (shm > 65536) {
+    hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_factor),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (a != hipSuccess) return a;
+  }
   hipLaunchKernelGGL(k_leaf_factor, dim3(2 * count), dim3(TBF), shm, s, ops, leaves, lidx, 0, G, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
