@@ -3,8 +3,9 @@
 // t owns row i = t % n and the columns c = g + G r (g = t / n, G = NT / n,
 // r < RE), so row quantities are per-thread scalars and no index division
 // happens in the elimination loop.  LDS carries only the pivot column, the two
-// rows being interchanged and the interchange record: a pivot step costs three
-// barriers and no global memory traffic.
+// rows being interchanged, the pivot's reciprocal (computed once, by one
+// thread) and the interchange record: a pivot step costs three barriers and
+// no global memory traffic.
 #pragma once
 
 #include "common.h"
@@ -15,6 +16,7 @@ struct Scratch {
   double2 colk[2][256];
   double2 rowk[2][256];
   double2 rowp[2][256];
+  double2 inv[2];
   int perm[256];
   int pos[256];
   int piv[2];
@@ -75,6 +77,7 @@ __device__ __forceinline__ void invert(double2 (&A)[RE], int n, const Layout& L,
         sc.piv[bsel] = bi;
         sc.perm[kk] = bi;
         if (best <= 0.0 && sc.flag == 0) sc.flag = kk + 1;
+        sc.inv[bsel] = best > 0.0 ? cdiv(mk(1.0, 0.0), sc.colk[bsel][bi]) : mk(0.0, 0.0);
       }
     }
     lds_barrier();
@@ -90,8 +93,7 @@ __device__ __forceinline__ void invert(double2 (&A)[RE], int n, const Layout& L,
     lds_barrier();
     // D: interchange rows kk and p, scale the pivot row, eliminate column kk elsewhere
     if (L.act) {
-      const double2 pv = sc.colk[bsel][p];
-      const double2 inv = cabs2(pv) > 0.0 ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+      const double2 inv = sc.inv[bsel];
       const bool is_k = L.i == kk, is_p = L.i == p;
       const double2 f = is_p ? sc.colk[bsel][kk] : sc.colk[bsel][L.i];
 #pragma unroll
@@ -146,6 +148,7 @@ __device__ __forceinline__ bool invert_diag(double2 (&A)[RE], int n, const Layou
         if (c < n) {
           if (c == kk) sc.colk[bsel][L.i] = A[r];
           if (L.i == kk) sc.rowk[bsel][c] = A[r];
+          if (c == kk && L.i == kk) sc.inv[bsel] = cabs2(A[r]) > 0.0 ? cdiv(mk(1.0, 0.0), A[r]) : mk(0.0, 0.0);
         }
       }
     }
@@ -154,7 +157,7 @@ __device__ __forceinline__ bool invert_diag(double2 (&A)[RE], int n, const Layou
     const double pa = cabs2(pv);
     if (tid == 0 && !(pa > 0.0)) sc.bad = 1;
     if (L.act) {
-      const double2 inv = pa > 0.0 ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+      const double2 inv = sc.inv[bsel];
       const bool is_k = L.i == kk;
       const double2 f = sc.colk[bsel][L.i];
       if (L.i > kk && L.g == kk % L.G && !(r2 * cabs2(f) <= pa)) sc.bad = 1;

@@ -68,11 +68,11 @@ __device__ __forceinline__ int eliminated(const BoxDev& B, int mode, int s, int 
 
 // Global-memory variant for wide boxes: S_j is formed in place of G_j and
 // inverted by the work-group with Gauss-Jordan elimination and partial
-// pivoting, by panels of FNB pivots held in shared memory (1024 threads).
-constexpr int TBF = 1024;
+// pivoting, by panels of FNB pivots held in shared memory (512 threads).
+constexpr int TBF = 512;
 constexpr int FNB = 16;
 
-size_t factor_shm(int b) { return sizeof(double2) * (2 * FNB * b + b + FNB) + sizeof(int) * b; }
+size_t factor_shm(int b) { return sizeof(double2) * (2 * FNB * b + b + 2 * FNB) + sizeof(int) * (2 * b + FNB); }
 __global__ void __launch_bounds__(TBF) k_leaf_factor(const OpDev* __restrict__ ops, const BoxDev* __restrict__ leaves,
                                                      const int* __restrict__ lidx, int mode,
                                                      c128* __restrict__ G, int* __restrict__ info) {
@@ -81,13 +81,18 @@ __global__ void __launch_bounds__(TBF) k_leaf_factor(const OpDev* __restrict__ o
   const OpDev op = ops[B.prob];
   const int b = B.ny;
   const int tid = threadIdx.x;
-  extern __shared__ unsigned char smem_raw[];
-  double2* pan = reinterpret_cast<double2*>(smem_raw);  // FNB b
-  double2* xk = pan + FNB * b;                          // FNB b
-  double2* fcol = xk + FNB * b;                         // b
-  double2* rowk = fcol + b;                             // FNB
-  int* perm = reinterpret_cast<int*>(rowk + FNB);       // b
+  // typed double2 so that the dynamic block starts 16-byte aligned after the
+  // static variables (misaligned 16-byte LDS accesses are split)
+  extern __shared__ double2 smem_d2[];
+  double2* work = smem_d2;                               // 2 FNB b
+  double2* fcol = work + 2 * FNB * b;                    // b
+  double2* rowk = fcol + b;                              // FNB
+  double2* rold = rowk + FNB;                            // FNB
+  int* src = reinterpret_cast<int*>(rold + FNB);         // b
+  int* tot = src + b;                                    // b
+  int* perm = tot + b;                                   // FNB
   __shared__ int s_piv;
+  __shared__ int s_any;
   __shared__ int s_flag;
   if (tid == 0) s_flag = 0;
   int first = 0;
@@ -118,7 +123,7 @@ __global__ void __launch_bounds__(TBF) k_leaf_factor(const OpDev* __restrict__ o
     }
     __syncthreads();
     const int flag_before = s_flag;
-    gj_inverse_blocked<TBF, FNB>(Gj, b, pan, xk, fcol, rowk, perm, &s_piv, &s_flag);
+    gj_inverse_blocked<TBF, FNB>(Gj, b, work, fcol, rowk, rold, src, tot, perm, &s_piv, &s_any, &s_flag);
     if (tid == 0 && first == 0 && flag_before == 0 && s_flag != 0) first = j * b + s_flag;
     __syncthreads();
   }
