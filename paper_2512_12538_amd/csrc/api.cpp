@@ -383,10 +383,10 @@ hh_status two_level(hh_ctx* c, int l, int q, const c128* r, c128* out) {
     if (P.rp_len < restrict_workspace(Ch.n_rchunks, Ch.rmax, q))
       return fail(c, HH_EDEVICE, "coarse restriction workspace smaller than the launch needs");
     HH_CHECK(launch_coarse_restrict(Ch.d, Ch.nbox, Ch.d_rchunks, Ch.d_rcbase, Ch.n_rchunks, P.d, P.dp, Ch.rmax, q, Ch.C,
-                                    P.T, P.RP, P.cvec, c->stream));
+                                    P.T, P.RP, P.cvec, c->act, c->stream));
     HH_CHECK(launch_coarse_gemv(P.dp, P.nbox, P.max_nc, q, P.Ainv, P.cvec, P.yvec, c->stream));
     HH_CHECK(launch_coarse_prolong(Ch.d, Ch.d_pgroups, Ch.n_pgroups, Ch.rmax, P.d, P.dp, q, Ch.C, P.yvec, out,
-                                   c->stream));
+                                   c->act, c->stream));
   }
   return HH_OK;
 }

@@ -384,17 +384,26 @@ constexpr int KU = 8;     // inner steps whose operands are loaded before their 
 // t[c][e] (a < 16 MT, c < 16 ncg).  Operands of KU steps of four nodes are
 // loaded before their products, so KU (1 + MT) loads per lane are in flight.
 // A wave's arithmetic does not depend on which items share its work-group.
+// Only the q real right-hand-side columns of a tile are written; with active
+// flags (problem * q + column) a wave none of whose columns is active returns
+// at once (the columns it owns belong to converged systems only).
 template <int MT>
 __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
                                                       const int2* __restrict__ chunks, int nitems, int ncg, int q,
                                                       const c128* __restrict__ C, const c128* __restrict__ t,
-                                                      c128* __restrict__ part) {
+                                                      c128* __restrict__ part, const int* __restrict__ active) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int item = blockIdx.x * (TB / 64) + wave;
   if (item >= nitems) return;
   const int g = item / ncg, cg = item - g * ncg;
   const int2 bc = chunks[g];
   const BoxDev B = child[bc.x];
+  if (active) {
+    // a wave whose right-hand sides are all converged leaves its tile as it is
+    bool any = false;
+    for (int cc = cg * 16; cc < q && cc < cg * 16 + 16; ++cc) any = any || active[B.prob * q + cc];
+    if (!any) return;
+  }
   const int e0 = bc.y * RCH;
   const BoxDev P = par[B.parent];
   const int m = lane & 15, kk = lane >> 4;
@@ -427,13 +436,15 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__
   }
   const int qpad = ncg * 16;
   c128* pb = part + (long long)g * (MT * 16) * qpad;
+  if (c < q) {
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
+    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int sl = 0; sl < 4; ++sl) {
-      const int a = mt * 16 + 4 * sl + (lane >> 4);
-      pb[(long long)a * qpad + c] = mk(re[mt][sl], im[mt][sl]);
-    }
+      for (int sl = 0; sl < 4; ++sl) {
+        const int a = mt * 16 + 4 * sl + (lane >> 4);
+        pb[(long long)a * qpad + c] = mk(re[mt][sl], im[mt][sl]);
+      }
+  }
 }
 
 // cvec[par][c][cidx + a] = sum over the child's chunks (in order) of part[g][a][c];
@@ -508,20 +519,27 @@ constexpr int PR_MAXR = 128;
 // groups of every child with a coarse space, numbered consecutively) and 64
 // right-hand sides (blockIdx.y); NTL tiles of 16 right-hand sides per wave
 // (fewer when q is small; an output's arithmetic is the same for any NTL).
+// With active flags a work-group none of whose right-hand sides is active
+// returns before any access.
 template <int NTL>
 __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
                                                      const ParentDev* __restrict__ pd,
                                                      const int2* __restrict__ groups, int q,
                                                      const c128* __restrict__ C, const c128* __restrict__ y,
-                                                     c128* __restrict__ u) {
+                                                     c128* __restrict__ u, const int* __restrict__ active) {
   const int2 bg = groups[blockIdx.x];
   const int box = bg.x;
   const BoxDev B = child[box];
   const int g0 = bg.y * (TB / 64) * 16;
   if (B.r == 0 || g0 >= B.n_own) return;
+  const int c0 = blockIdx.y * 64;
+  if (active) {
+    bool any = false;
+    for (int cc = c0; cc < q && cc < c0 + 64; ++cc) any = any || active[B.prob * q + cc];
+    if (!any) return;
+  }
   const BoxDev P = par[B.parent];
   const ParentDev D = pd[B.parent];
-  const int c0 = blockIdx.y * 64;
   extern __shared__ double2 ys[];  // ys[c][a], 64 x (r + 1)
   const int rs = B.r + 1;
   for (int idx = threadIdx.x; idx < 64 * B.r; idx += TB) {
@@ -658,7 +676,7 @@ long long restrict_workspace(int nchunks, int rmax, int q) {
 
 hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* chunks, const int* cbase, int nchunks,
                                   const BoxDev* par, const ParentDev* pd, int rmax, int q, const c128* C,
-                                  const c128* t, c128* part, c128* cvec, hipStream_t s) {
+                                  const c128* t, c128* part, c128* cvec, const int* active, hipStream_t s) {
   if (nchild <= 0 || nchunks <= 0 || rmax <= 0 || q <= 0) return hipSuccess;
   const int mt = restrict_tiles(rmax);
   if (mt == 0) return hipErrorInvalidValue;
@@ -667,11 +685,14 @@ hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* c
   if (nitems > (1LL << 30)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((nitems + TB / 64 - 1) / (TB / 64)));
   if (mt == 2)
-    hipLaunchKernelGGL(k_restrict_mfma<2>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part);
+    hipLaunchKernelGGL(k_restrict_mfma<2>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part,
+                       active);
   else if (mt == 4)
-    hipLaunchKernelGGL(k_restrict_mfma<4>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part);
+    hipLaunchKernelGGL(k_restrict_mfma<4>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part,
+                       active);
   else
-    hipLaunchKernelGGL(k_restrict_mfma<8>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part);
+    hipLaunchKernelGGL(k_restrict_mfma<8>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part,
+                       active);
   hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + TB - 1) / TB, nchild), dim3(TB), 0, s, child, pd, cbase,
                      16 * mt, q, ncg * 16, part, cvec);
   return hipGetLastError();
@@ -689,7 +710,7 @@ int prolong_group_nodes() { return (TB / 64) * 16; }
 
 hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ngroups, int rmax, const BoxDev* par,
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
-                                 hipStream_t s) {
+                                 const int* active, hipStream_t s) {
   if (ngroups <= 0 || q <= 0) return hipSuccess;
   if (rmax > PR_MAXR) return hipErrorInvalidValue;
   const size_t shm = sizeof(double2) * 64 * (size_t)(rmax + 1);
@@ -702,10 +723,10 @@ hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ng
   }
   const dim3 grid(ngroups, (q + 63) / 64);
   if (q <= 16)
-    hipLaunchKernelGGL(k_prolong_mfma<1>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u);
+    hipLaunchKernelGGL(k_prolong_mfma<1>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u, active);
   else if (q <= 32)
-    hipLaunchKernelGGL(k_prolong_mfma<2>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u);
+    hipLaunchKernelGGL(k_prolong_mfma<2>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u, active);
   else
-    hipLaunchKernelGGL(k_prolong_mfma<4>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u);
+    hipLaunchKernelGGL(k_prolong_mfma<4>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u, active);
   return hipGetLastError();
 }

@@ -106,11 +106,13 @@ hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* 
 // `part` (restrict_workspace(nchunks, rmax, q) entries), then an ordered sum
 // over each child's chunks.  chunks[g] = (child, chunk index) for the chunks of
 // every child with a coarse space, child-major; cbase[child] = its first chunk.
+// active (nullable): flags per system (problem * q + column); results for
+// inactive systems are left undefined, as in the leaf sweeps.
 int restrict_chunk_nodes();
 long long restrict_workspace(int nchunks, int rmax, int q);
 hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* chunks, const int* cbase, int nchunks,
                                   const BoxDev* par, const ParentDev* pd, int rmax, int q, const c128* C,
-                                  const c128* t, c128* part, c128* cvec, hipStream_t s);
+                                  const c128* t, c128* part, c128* cvec, const int* active, hipStream_t s);
 // y[par][c] = A_c^{-1} cvec[par][c] (FP64 matrix cores)
 hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, const c128* Ainv,
                               const c128* cvec, c128* y, hipStream_t s);
@@ -120,7 +122,7 @@ hipError_t launch_coarse_gemv(const ParentDev* pd, int npar, int max_nc, int q, 
 int prolong_group_nodes();
 hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ngroups, int rmax, const BoxDev* par,
                                  const ParentDev* pd, int q, const c128* C, const c128* y, c128* u,
-                                 hipStream_t s);
+                                 const int* active, hipStream_t s);
 
 // ---------------------------------------------------------------- Krylov (k_krylov.hip)
 // The systems of the outer loop (one per problem and right-hand side): system
