@@ -210,14 +210,15 @@ hipError_t launch_reg(const OpDev* ops, const BoxDev* leaves, int nleaf, const i
 }  // namespace
 
 // Register-slot class of a leaf of width ny (the kernel variant that holds
-// its rows; 6: the global-memory variant).
+// its rows: 1024 threads, at most 4 or 6 entries per thread; 6: the
+// global-memory variant).  The chains are few and sequential, so the widest
+// work-group that holds the matrix hides the most latency per pivot step.
 int leaf_factor_bucket(int ny) {
   if (ny > 256) return 6;
-  const int G512 = 512 / ny;
-  const int re = G512 > 0 ? (ny + G512 - 1) / G512 : 1 << 30;
-  if (re <= 8) return 0;
-  if (re <= 10) return 1;
-  if (re <= 12) return 2;
+  const int G = 1024 / ny;
+  const int re = G > 0 ? (ny + G - 1) / G : 1 << 30;
+  if (re <= 4) return 0;
+  if (re <= 6) return 1;
   return 6;  // wider rows would spill the register tile: the global-memory variant
 }
 
@@ -228,9 +229,8 @@ hipError_t launch_leaf_factor(const OpDev* ops, const BoxDev* leaves, int nleaf,
                               int max_ny, c128* G, int* info, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   switch (leaf_factor_bucket(max_ny)) {
-    case 0: return launch_reg<512, 8>(ops, leaves, nleaf, lidx, count, G, info, s);
-    case 1: return launch_reg<512, 10>(ops, leaves, nleaf, lidx, count, G, info, s);
-    case 2: return launch_reg<512, 12>(ops, leaves, nleaf, lidx, count, G, info, s);
+    case 0: return launch_reg<1024, 4>(ops, leaves, nleaf, lidx, count, G, info, s);
+    case 1: return launch_reg<1024, 6>(ops, leaves, nleaf, lidx, count, G, info, s);
     default: break;
   }
   if (max_ny > 256) return hipErrorInvalidValue;
