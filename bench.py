@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--nrhs", type=int, default=64)
+    ap.add_argument("--lanes", type=int, default=2,
+                    help="host threads (one stream and one context per step each) running steps concurrently")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -62,6 +64,7 @@ def parse():
                     help="independent problems of the batched measurement (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2, help="timed steps of the batched measurement")
     ap.add_argument("--no-steady", action="store_true", help="skip the steady-state (cached setup) solve measurement")
+    ap.add_argument("--no-serial", action="store_true", help="skip the one-lane comparison run")
     return ap.parse_args()
 
 
@@ -76,10 +79,10 @@ def make_inputs(hh, torch, nrhs, seed=1):
     return torch.from_numpy(f).to("cuda"), torch.from_numpy(om).to("cuda"), f
 
 
-def one_step(hh, fd, om, u, precision, phases=None, prof=None):
+def one_step(hh, fd, om, u, precision, phases=None, prof=None, stream=None):
     t0 = time.perf_counter()
     ctx = hh.hh_setup(2, CFG["N"], CFG["k"], hh.decomposition(CFG["m"], CFG["overlap"]), precision=precision,
-                      outer=hh.HH_GMRES, gmres_restart=CFG["restart"])
+                      outer=hh.HH_GMRES, gmres_restart=CFG["restart"], stream=stream)
     t1 = time.perf_counter()
     hh.hh_build_coarse(ctx, 1, CFG["rank"], CFG["oversample"], om)
     t2 = time.perf_counter()
@@ -103,58 +106,112 @@ def one_step(hh, fd, om, u, precision, phases=None, prof=None):
     return info
 
 
-def run_gpu(hh, torch, nrhs, precision, steps, warmup, profile):
+def run_gpu(hh, torch, nrhs, precision, steps, warmup, profile, lanes=1):
+    """Steps of the whole path on `lanes` host threads, each with its own stream and context per step, so that the
+    set-up and coarse build of one step (latency-bound, few work-groups) overlap the solve of another (bandwidth-bound
+    Krylov passes).  Warm-up and timed steps are dealt round-robin to the lanes."""
+    import threading
+
     fd, om, f = make_inputs(hh, torch, nrhs)
-    u = torch.zeros_like(fd)
-    for _ in range(warmup):
-        one_step(hh, fd, om, u, precision)
+    lanes = max(1, lanes)
+    streams = [torch.cuda.Stream() for _ in range(lanes)]
+    us = [torch.zeros_like(fd) for _ in range(lanes)]
     torch.cuda.synchronize()
+    lock = threading.Lock()
     phases = {"setup": [], "build_coarse": [], "solve": []}
     prof = {} if profile else None
     lat = []
-    iters = None
+    iters = []
+    errors = []
+
+    def lane(k, count, record):
+        try:
+            with torch.cuda.stream(streams[k]):
+                for _ in range(count):
+                    ph = {"setup": [], "build_coarse": [], "solve": []} if record else None
+                    pr = {} if (record and profile) else None
+                    ts = time.perf_counter()
+                    info = one_step(hh, fd, om, us[k], precision, ph, pr, streams[k])
+                    dt = time.perf_counter() - ts
+                    if not all(i[1] for i in info):
+                        raise RuntimeError("a right-hand side did not converge")
+                    if record:
+                        with lock:
+                            lat.append(dt)
+                            iters[:] = [i[0] for i in info]
+                            for key, v in ph.items():
+                                phases[key].extend(v)
+                            if pr is not None:
+                                for fam, acc in pr.items():
+                                    tot = prof.setdefault(fam, [0, 0.0, 0.0, 0.0])
+                                    for j in range(4):
+                                        tot[j] += acc[j]
+        except BaseException as e:  # noqa: BLE001 - re-raised on the main thread
+            errors.append(e)
+
+    def run_lanes(total, record):
+        counts = [total // lanes + (1 if k < total % lanes else 0) for k in range(lanes)]
+        threads = [threading.Thread(target=lane, args=(k, counts[k], record)) for k in range(lanes) if counts[k] > 0]
+        for t in threads:
+            t.start()
+        for t in threads:
+            t.join()
+        if errors:
+            raise errors[0]
+
+    run_lanes(warmup, False)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        ts = time.perf_counter()
-        info = one_step(hh, fd, om, u, precision, phases, prof)
-        lat.append(time.perf_counter() - ts)
-        iters = [i[0] for i in info]
-        assert all(i[1] for i in info)
+    run_lanes(steps, True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return dict(wall=wall, phases=phases, lat=lat, iters=iters, u=u, f=f, prof=prof)
+    return dict(wall=wall, phases=phases, lat=lat, iters=iters, u=us[0], f=f, prof=prof, lanes=lanes)
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_helm2d_n256_k40_4x4.md")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2512_12538_amd", "csrc", f) for f in ("k_sweep.hip", "common.h")]
+CSRC = os.path.join(ROOT, "paper_2512_12538_amd", "csrc")
+# HBM traffic per launch of each kernel family, from the committed counter summaries, and the sources it depends on
+TRAFFIC = {
+    0: (os.path.join(ROOT, "profiles", "k_sweep_helm2d_n256_k40_4x4.md"),
+        [os.path.join(CSRC, f) for f in ("k_sweep.hip", "common.h")]),
+    1: (os.path.join(ROOT, "profiles", "k_basis_update_k_dot_partial_helm2d_n256_k40_4x4.md"),
+        [os.path.join(CSRC, f) for f in ("k_krylov.hip", "common.h")]),
+    2: (os.path.join(ROOT, "profiles", "k_basis_update_k_dot_partial_helm2d_n256_k40_4x4.md"),
+        [os.path.join(CSRC, f) for f in ("k_krylov.hip", "common.h")]),
+}
 
 
-def measured_traffic(nrhs, precision):
-    """HBM bytes per leaf solve (phase 1 + phase 2 dispatches) from the committed FETCH_SIZE / WRITE_SIZE passes,
-    scaled by the copy calibration; None when the kernel source or the workload differs."""
+def measured_traffic(fam, nrhs, precision, lanes):
+    """HBM bytes per launch of kernel family fam from the committed FETCH_SIZE / WRITE_SIZE passes, scaled by the
+    copy calibration; None when there is no summary for it or the kernel source or the workload differs."""
     import hashlib
 
+    if fam not in TRAFFIC:
+        return None
+    path, sources = TRAFFIC[fam]
     try:
         fig = {}
-        for line in open(TRAFFIC_FILE):
+        for line in open(path):
             k, sep, v = line.strip().partition(": ")
             if sep:
                 fig[k] = v
         h = hashlib.sha256()
-        for f in KERNEL_SOURCES:
+        for f in sources:
             h.update(open(f, "rb").read())
     except OSError:
         return None
     if fig.get("kernel_source_sha256") != h.hexdigest():
         return None
-    if fig.get("rhs_per_step") != str(nrhs) or fig.get("precision") != precision:
+    if fig.get("rhs_per_step") != str(nrhs) or fig.get("precision") != precision or fig.get("lanes") != str(lanes):
         return None
-    fetch = float(fig["fetch_kib_per_launch"]) * float(fig["fetch_scale"])
-    write = float(fig["write_kib_per_launch"]) * float(fig["write_scale"])
+    try:
+        fetch = float(fig[f"family_{fam}_fetch_kib_per_launch"]) * float(fig["fetch_scale"])
+        write = float(fig[f"family_{fam}_write_kib_per_launch"]) * float(fig["write_scale"])
+    except KeyError:
+        return None
     return round((fetch + write) * 1024.0)
 
 
-def roofline(prof, precision, nrhs):
+def roofline(prof, precision, nrhs, lanes):
     if not prof:
         return None
     fam = max(prof, key=lambda k: prof[k][1])
@@ -174,10 +231,15 @@ def roofline(prof, precision, nrhs):
         achieved = bytes_launch / avg_s / 1e9
         out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(achieved / HBM_PEAK_GBS, 4)}
-    out.update({"traffic": measured_traffic(nrhs, precision) if fam == 0 else None, "kernel": FAMILY[fam], "launches": int(n),
+    out.update({"traffic": measured_traffic(fam, nrhs, precision, lanes), "kernel": FAMILY[fam], "launches": int(n),
                 "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes_per_launch": round(bytes_launch),
                 "algorithmic_flops_per_launch": round(flops_launch), "intensity_flop_per_byte": round(intensity, 2),
-                "other_families_ms": {FAMILY[k]: round(v[1], 2) for k, v in prof.items() if k != fam}})
+                "other_families_ms": {FAMILY[k]: round(v[1], 2) for k, v in prof.items() if k != fam},
+                "families": {FAMILY[k]: {"launches": int(v[0]), "total_ms": round(v[1], 2),
+                                         "avg_launch_us": round(1000.0 * v[1] / v[0], 2) if v[0] else None,
+                                         "algorithmic_bytes_per_launch": round(v[2] / v[0]) if v[0] else None,
+                                         "traffic": measured_traffic(k, nrhs, precision, lanes)}
+                             for k, v in prof.items()}})
     return out
 
 
@@ -456,7 +518,7 @@ def main():
     import paper_2512_12538_amd as hh
 
     prec = hh.HH_MIXED if args.precision == "mixed" else hh.HH_FP64
-    res = run_gpu(hh, torch, args.nrhs, prec, args.steps, args.warmup, not args.no_profile)
+    res = run_gpu(hh, torch, args.nrhs, prec, args.steps, args.warmup, not args.no_profile, args.lanes)
     wall = res["wall"]
     ms_per_step = 1000.0 * wall / args.steps
     value = args.nrhs * args.steps / wall
@@ -480,17 +542,34 @@ def main():
             "rank_per_interface": CFG["rank"], "oversample": CFG["oversample"], "rhs_per_step": args.nrhs,
             "outer": f"gmres({CFG['restart']})", "rtol": CFG["rtol"], "precision": args.precision,
             "step": "hh_setup + hh_build_coarse + hh_solve of the RHS batch",
+            "lanes": res["lanes"],
+            "lanes_note": "steps run on this many host threads, each with its own stream, so one step's set-up and "
+                          "coarse build overlap another's solve; latency and phases are per step under that overlap",
         },
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3), "p99": round(float(np.percentile(lat, 99)), 3)},
         "phases_ms": {k: round(1000.0 * float(np.mean(v)), 3) for k, v in res["phases"].items()},
         "gmres_iterations": {"min": int(min(res["iters"])), "max": int(max(res["iters"])),
                              "mean": round(float(np.mean(res["iters"])), 2)},
         "solve_only_solves_per_s": round(args.nrhs / float(np.mean(res["phases"]["solve"])), 3),
-        "roofline": roofline(res["prof"], args.precision, args.nrhs),
+        "roofline": roofline(res["prof"], args.precision, args.nrhs, res["lanes"]),
     }
     section_done(torch, "main workload")
+    if res["lanes"] > 1 and not args.no_serial:
+        sres = run_gpu(hh, torch, args.nrhs, prec, max(2, args.steps // 2), 1, not args.no_profile, 1)
+        slat = np.array(sres["lat"]) * 1000.0
+        out["serial"] = {
+            "note": "the same steps one after another on one stream",
+            "value": round(args.nrhs * len(sres["lat"]) / sres["wall"], 3),
+            "ms_per_step": round(1000.0 * sres["wall"] / len(sres["lat"]), 3),
+            "latency_ms": {"p50": round(float(np.percentile(slat, 50)), 3),
+                           "p99": round(float(np.percentile(slat, 99)), 3)},
+            "phases_ms": {k: round(1000.0 * float(np.mean(v)), 3) for k, v in sres["phases"].items()},
+            "solve_only_solves_per_s": round(args.nrhs / float(np.mean(sres["phases"]["solve"])), 3),
+            "roofline": roofline(sres["prof"], args.precision, args.nrhs, 1),
+        }
+        section_done(torch, "serial steps")
     if not args.no_mixed and args.precision == "fp64":
-        mres = run_gpu(hh, torch, args.nrhs, hh.HH_MIXED, max(2, args.steps // 2), 1, False)
+        mres = run_gpu(hh, torch, args.nrhs, hh.HH_MIXED, max(2, args.steps // 2), res["lanes"], False, res["lanes"])
         mlat = np.array(mres["lat"]) * 1000.0
         out["mixed"] = {
             "value": round(args.nrhs * len(mres["lat"]) / mres["wall"], 3),
