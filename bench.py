@@ -363,6 +363,7 @@ def serving(hh, torch, precision, seconds, rate, drain=30.0, seed=11):
               flush=True)
     wall = time.perf_counter() - t0
     stats = srv.stats()
+    last_error = srv.last_error()
     srv.close()  # drops what is still queued; running batches end first
     fin = [(x, r) for x, r in zip(sched, results) if r is not None]
     lat = np.array([r["latency_s"] for _, r in fin] + [np.inf] * (len(sched) - len(fin))) * 1000.0
@@ -384,7 +385,17 @@ def serving(hh, torch, precision, seconds, rate, drain=30.0, seed=11):
         "mean_batch_rhs": round(float(np.mean([r["batch_rhs"] for _, r in fin])), 2) if fin else None,
         "cache_hit_rate": round(float(np.mean([r["cache_hit"] for _, r in fin])), 3) if fin else None,
         "operators_set_up": stats["misses"], "evictions": stats["evictions"],
+        "status_by_side": _status_by_side(hh, fin),
+        "last_batch_error": last_error or None,
     }
+
+
+def _status_by_side(hh, fin):
+    out = {}
+    for x, r in fin:
+        key = f"{SERVING_SIDES[x[1]][0]}:{hh._STATUS[r['status']]}"
+        out[key] = out.get(key, 0) + 1
+    return dict(sorted(out.items()))
 
 
 def batched(hh, torch, precision, count, steps, warmup=1, seed=4):

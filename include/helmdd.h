@@ -28,8 +28,10 @@
  *     which returns it to a process-wide cache of device blocks that later
  *     contexts reuse (hh_release_cached_memory frees the cache).
  *   - All device work is enqueued on hh_options.stream (null: the default
- *     stream).  Calls return after the work they started has completed,
- *     except where stated.  A context is used by one host thread at a time.
+ *     stream), which must stay valid until hh_destroy returns.  Calls return
+ *     after the work they started has completed, except where stated.  A
+ *     context is used by one host thread at a time; separate contexts may be
+ *     used concurrently from separate threads and streams.
  *   - On HH_EDEVICE the context is poisoned: only hh_destroy is valid.
  */
 #ifndef HELMDD_H
@@ -261,6 +263,10 @@ hh_status hh_server_submit(hh_server* s, const hh_request* r, uint64_t* ticket);
 hh_status hh_server_wait(hh_server* s, uint64_t ticket, double timeout_s, hh_request_result* res);
 hh_status hh_server_stats(hh_server* s, int64_t* served, int64_t* misses, int64_t* evictions, int64_t* cached,
                           int64_t* reserved_bytes);
+/* Message of the server's last failed batch (status, operator id, batch width
+ * and the context's or set-up's error text), or "" when none failed.  The
+ * pointer is valid on the calling thread until its next call of this function. */
+const char* hh_server_last_error(hh_server* s);
 /* Stops the workers after their running batches; queued requests are dropped. */
 hh_status hh_server_destroy(hh_server* s);
 
@@ -285,6 +291,10 @@ hh_status hh_omega_philox(uint64_t seed, int32_t level, int32_t box, int32_t m_i
  * memory, or HH_POOL_CAP_GB gigabytes when that environment variable is set
  * (read at the first allocation on the device). */
 hh_status hh_release_cached_memory(int64_t* bytes);
+/* Message of the last failed call on context c; with c = NULL, the message of
+ * the calling thread's last failed hh_setup / hh_setup_batch (whose context no
+ * longer exists), or "null context".  The pointer stays valid until the next
+ * call on c (or the next set-up on this thread). */
 const char* hh_last_error(const hh_ctx* c);
 const char* hh_status_string(hh_status s);
 

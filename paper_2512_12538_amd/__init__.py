@@ -124,6 +124,8 @@ def _load():
         fn.restype = ctypes.c_int
     lib.hh_last_error.argtypes = [P]
     lib.hh_last_error.restype = ctypes.c_char_p
+    lib.hh_server_last_error.argtypes = [P]
+    lib.hh_server_last_error.restype = ctypes.c_char_p
     return lib
 
 
@@ -146,9 +148,9 @@ def load():
     return _lib.hh_setup
 
 
-def _check(status: int, ctx=None) -> None:
+def _check(status: int, ctx=None, setup: bool = False) -> None:
     if status != HH_OK:
-        msg = _lib.hh_last_error(ctx).decode() if ctx else ""
+        msg = _lib.hh_last_error(ctx).decode() if (ctx or setup) else ""
         raise HelmddError(status, msg)
 
 
@@ -236,7 +238,7 @@ def hh_setup(dim: int, n_cells: int, k, decomp: hh_decomposition, precision: int
     ctx = ctypes.c_void_p()
     if keep is not None and keep.size != (n_cells + 1) ** dim:
         raise ValueError("k must hold one value per node")
-    _check(_lib.hh_setup(ctypes.byref(op), ctypes.byref(decomp), ctypes.byref(opts), ctypes.byref(ctx)))
+    _check(_lib.hh_setup(ctypes.byref(op), ctypes.byref(decomp), ctypes.byref(opts), ctypes.byref(ctx)), setup=True)
     del keep
     return Context(ctx, dim, n_cells)
 
@@ -274,7 +276,7 @@ def hh_setup_batch(dim: int, problems, precision: int = HH_FP64, outer: int = HH
     st = stream if stream is not None else torch.cuda.current_stream()
     opts.stream = ctypes.c_void_p(st.cuda_stream)
     ctx = ctypes.c_void_p()
-    _check(_lib.hh_setup_batch(nprob, ops, decs, ctypes.byref(opts), ctypes.byref(ctx)))
+    _check(_lib.hh_setup_batch(nprob, ops, decs, ctypes.byref(opts), ctypes.byref(ctx)), setup=True)
     del keep
     c = Context(ctx, dim, [int(pr[0]) for pr in problems])
     nn = np.zeros(nprob, np.int64)
@@ -488,6 +490,10 @@ class Server:
         return dict(status=int(res.status), iters=int(res.iters), rel_residual=float(res.rel_residual),
                     latency_s=float(res.latency_s), queue_s=float(res.queue_s), batch_rhs=int(res.batch_rhs),
                     cache_hit=bool(res.cache_hit))
+
+    def last_error(self) -> str:
+        """Message of the last failed batch ("" when none failed)."""
+        return _lib.hh_server_last_error(self.handle).decode()
 
     def stats(self) -> dict:
         v = [ctypes.c_int64(0) for _ in range(5)]

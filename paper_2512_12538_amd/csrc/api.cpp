@@ -456,11 +456,19 @@ hh_status solve_level(hh_ctx* c, int l, int q, const c128* rhs, c128* x) {
   return HH_OK;
 }
 
+// Entry points start here: a HIP error left in this thread's last-error slot by an
+// earlier, unrelated call (the caller's own or a failed allocation handled
+// elsewhere) is cleared, so that the checks after this call's launches see only
+// their own errors.
 hh_status check_usable(hh_ctx* c) {
   if (!c) return HH_EINVAL;
+  (void)hipGetLastError();
   if (c->poisoned) return fail(c, HH_EDEVICE, "context poisoned by an earlier device error: " + c->err);
   return HH_OK;
 }
+
+// message of this thread's last failed set-up (its context no longer exists)
+thread_local std::string t_setup_err;
 
 hh_status check_built(hh_ctx* c) {
   for (int l = 1; l <= c->L; ++l)
@@ -535,7 +543,10 @@ const char* hh_status_string(hh_status s) {
   return "unknown";
 }
 
-const char* hh_last_error(const hh_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* hh_last_error(const hh_ctx* c) {
+  if (c) return c->err.c_str();
+  return t_setup_err.empty() ? "null context" : t_setup_err.c_str();
+}
 
 hh_status hh_destroy(hh_ctx* c) {
   if (!c) return HH_OK;
@@ -550,8 +561,12 @@ hh_status hh_destroy(hh_ctx* c) {
     (void)hipEventDestroy(r.b);
   }
   if (c->poll) (void)hipHostFree(c->poll);
-  for (const DevBuf& b : c->allocs) devpool::release(b.p, b.bytes, c->stream);
+  // the stream was synchronised above: the blocks go back idle, and blocks this
+  // context released earlier stop referring to the stream (the caller may
+  // destroy it once its contexts are gone)
+  for (const DevBuf& b : c->allocs) devpool::release(b.p, b.bytes, c->stream, true);
   c->allocs.clear();
+  devpool::forget_stream(c->stream);
   delete c;
   (void)hipGetLastError();  // clean-up ignores errors; leave none behind for the caller's next call
   return HH_OK;
@@ -569,6 +584,8 @@ hh_status hh_setup(const hh_operator* A, const hh_decomposition* d, const hh_opt
 
 hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposition* d, const hh_options* o,
                          hh_ctx** out) {
+  t_setup_err.clear();
+  (void)hipGetLastError();
   if (!A || !d || !out || nprob < 1) return HH_EINVAL;
   *out = nullptr;
   std::vector<Geometry> parts(nprob);
@@ -612,6 +629,7 @@ hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposi
     for (int l = 1; l <= c->L; ++l) c->inner[l] = std::max(c->inner[l], std::max(1, (int)d[p].inner_iters[l - 1]));
   hh_status st = HH_OK;
   auto bail = [&](hh_status s) {
+    t_setup_err = c->err;
     hh_destroy(c);
     return s;
   };
@@ -680,8 +698,7 @@ hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposi
   Level& leaf = c->lv[c->L];
   if (leaf.max_ny > 256) {
     c->err = "leaf boxes wider than 256 nodes along q are not supported";
-    hh_destroy(c);
-    return HH_EUNSUPPORTED;
+    return bail(HH_EUNSUPPORTED);
   }
   long long goff = 0;
   for (BoxDev& b : leaf.hb) {
@@ -714,8 +731,7 @@ hh_status hh_setup_batch(int32_t nprob, const hh_operator* A, const hh_decomposi
     if (info[i] != 0) {
       const int lf = i < 2 * leaf.nbox ? i / 2 : i - 2 * leaf.nbox;
       c->err = "zero pivot in the factorisation of leaf " + std::to_string(lf);
-      hh_destroy(c);
-      return HH_ESINGULAR;
+      return bail(HH_ESINGULAR);
     }
   if (c->precision == HH_MIXED) {
     if ((st = dalloc(c, &c->G32, (size_t)(goff + gpad))) != HH_OK) return bail(st);

@@ -231,69 +231,90 @@ __global__ void __launch_bounds__(1024) k_gj_panel(const ParentDev* __restrict__
   c128* A = Aall + P.aoff;
   int* perm = perm_all + (long long)blockIdx.x * max_nc;
   int* sig = sig_all + (long long)blockIdx.x * max_nc;
-  extern __shared__ double2 pan[];  // pan[t * n + i], t < kb
+  // shared: pan[t * n + i] (t < kb), fcol[n], rowk[GJ_NB], rold[GJ_NB], ssig[n]
+  extern __shared__ double2 pan[];
   double2* fcol = pan + (long long)GJ_NB * n;
-  __shared__ int s_p;
-  __shared__ double2 s_inv;
+  double2* rowk = fcol + n;
+  double2* rold = rowk + GJ_NB;
+  int* ssig = reinterpret_cast<int*>(rold + GJ_NB);
+  __shared__ int s_p, s_flag;
   const int tid = threadIdx.x, NT = blockDim.x;
-  for (int e = tid; e < kb * n; e += NT) pan[e] = A[(e % n) + (long long)(k0 + e / n) * n];
-  for (int i = tid; i < n; i += NT) sig[i] = i;
+  // element (i, c) of this thread's first slot and the stride between slots
+  const int i0 = tid % n, c0 = tid / n, di = NT % n, dc = NT / n;
+  {
+    int i = i0, c = c0;
+    while (c < kb) {
+      pan[i + c * n] = A[i + (long long)(k0 + c) * n];
+      i += di;
+      c += dc;
+      if (i >= n) { i -= n; c += 1; }
+    }
+  }
+  for (int i = tid; i < n; i += NT) ssig[i] = i;
+  if (tid == 0) s_flag = 0;
   __syncthreads();
+  // two barriers a pivot: the first wave finds the pivot and stages the step
+  // (scaled pivot row, old row kk, multipliers of the interchanged column),
+  // then every thread updates the panel with the interchange folded in
   for (int t = 0; t < kb; ++t) {
     const int kk = k0 + t;
-    double2* col = pan + (long long)t * n;
+    const double2* col = pan + (long long)t * n;
     if (tid < 64) {
       double best = -1.0;
-      int bi = kk;
+      int p = kk;
       for (int i = kk + tid; i < n; i += 64) {
         const double a = cabs2(col[i]);
-        if (a > best) { best = a; bi = i; }
+        if (a > best) { best = a; p = i; }
       }
       for (int o = 32; o > 0; o >>= 1) {
         const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        const int oi = __shfl_xor(p, o, 64);
+        if (ob > best || (ob == best && oi < p)) { best = ob; p = oi; }
       }
+      const double2 pv = col[p];
+      const double2 inv = cabs2(pv) > 0.0 ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
+      for (int c = tid; c < kb; c += 64) {
+        rold[c] = pan[(long long)c * n + kk];
+        rowk[c] = (c == t) ? inv : cmul(pan[(long long)c * n + p], inv);
+      }
+      for (int i = tid; i < n; i += 64) fcol[i] = (i == kk) ? mk(0.0, 0.0) : (i == p ? col[kk] : col[i]);
       if (tid == 0) {
-        s_p = bi;
-        perm[kk] = bi;
-        if (best <= 0.0 && info[blockIdx.x] == 0) info[blockIdx.x] = kk + 1;
-        const int tmp = sig[kk];
-        sig[kk] = sig[bi];
-        sig[bi] = tmp;
+        s_p = p;
+        perm[kk] = p;
+        if (best <= 0.0 && s_flag == 0) s_flag = kk + 1;
+        const int tmp = ssig[kk];
+        ssig[kk] = ssig[p];
+        ssig[p] = tmp;
       }
     }
     __syncthreads();
-    const int pr = s_p;
-    if (pr != kk)
-      for (int c = tid; c < kb; c += NT) {
-        const double2 x = pan[(long long)c * n + kk];
-        pan[(long long)c * n + kk] = pan[(long long)c * n + pr];
-        pan[(long long)c * n + pr] = x;
+    const int p = s_p;
+    int i = i0, c = c0;
+    while (c < kb) {
+      const int e = i + c * n;
+      if (i == kk) {
+        pan[e] = rowk[c];
+      } else {
+        const double2 base = (c == t) ? mk(0.0, 0.0) : (i == p ? rold[c] : pan[e]);
+        pan[e] = csub(base, cmul(fcol[i], rowk[c]));
       }
-    __syncthreads();
-    if (tid == 0) {
-      const double2 pv = col[kk];
-      s_inv = cabs2(pv) > 0.0 ? cdiv(mk(1.0, 0.0), pv) : mk(0.0, 0.0);
-    }
-    __syncthreads();
-    const double2 inv = s_inv;
-    for (int i = tid; i < n; i += NT) fcol[i] = (i == kk) ? mk(0.0, 0.0) : col[i];
-    __syncthreads();
-    for (int c = tid; c < kb; c += NT) {
-      double2& x = pan[(long long)c * n + kk];
-      x = (c == t) ? inv : cmul(x, inv);
-    }
-    __syncthreads();
-    for (int e = tid; e < kb * n; e += NT) {
-      const int i = e % n, c = e / n;
-      if (i == kk) continue;
-      const double2 base = (c == t) ? mk(0.0, 0.0) : pan[e];
-      pan[e] = csub(base, cmul(fcol[i], pan[(long long)c * n + kk]));
+      i += di;
+      c += dc;
+      if (i >= n) { i -= n; c += 1; }
     }
     __syncthreads();
   }
-  for (int e = tid; e < kb * n; e += NT) A[(e % n) + (long long)(k0 + e / n) * n] = pan[e];
+  {
+    int i = i0, c = c0;
+    while (c < kb) {
+      A[i + (long long)(k0 + c) * n] = pan[i + c * n];
+      i += di;
+      c += dc;
+      if (i >= n) { i -= n; c += 1; }
+    }
+  }
+  for (int i = tid; i < n; i += NT) sig[i] = ssig[i];
+  if (tid == 0 && s_flag != 0 && info[blockIdx.x] == 0) info[blockIdx.x] = s_flag;
 }
 
 __global__ void __launch_bounds__(256) k_gj_trail(const ParentDev* __restrict__ pars, c128* __restrict__ Aall,
@@ -631,10 +652,15 @@ hipError_t launch_gj_inverse(const ParentDev* pars, int npar, int max_nc, c128* 
   if (npar <= 0 || max_nc <= 0) return hipSuccess;
   hipError_t e = launch_fill_zero(info, (long long)sizeof(int) * npar, s);
   if (e != hipSuccess) return e;
-  const size_t shm = sizeof(double2) * (size_t)(GJ_NB + 1) * max_nc;
-  if (max_nc <= GJ_MAXN &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(k_gj_panel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)shm) == hipSuccess) {
+  auto panel_shm = [](int n) {
+    return sizeof(double2) * ((size_t)(GJ_NB + 1) * n + 2 * GJ_NB) + sizeof(int) * (size_t)n;
+  };
+  const size_t shm = panel_shm(max_nc);
+  // raised once, to the largest panel (a per-call setting could be lowered by a
+  // concurrent caller between another caller's setting and its launch)
+  static const hipError_t raised = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(k_gj_panel), hipFuncAttributeMaxDynamicSharedMemorySize, (int)panel_shm(GJ_MAXN));
+  if (max_nc <= GJ_MAXN && (shm <= 65536 || raised == hipSuccess)) {
     // blocked: two launches per panel of GJ_NB pivots (fcol holds the permutations)
     int* sig = reinterpret_cast<int*>(fcol);
     for (int k0 = 0; k0 < max_nc; k0 += GJ_NB) {
@@ -714,13 +740,17 @@ hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ng
   if (ngroups <= 0 || q <= 0) return hipSuccess;
   if (rmax > PR_MAXR) return hipErrorInvalidValue;
   const size_t shm = sizeof(double2) * 64 * (size_t)(rmax + 1);
-  if (shm > 65536) {
+  // raised once, to the largest rank (see launch_gj_inverse)
+  static const hipError_t raised = [] {
+    const int most = (int)(sizeof(double2) * 64 * (PR_MAXR + 1));
     for (const void* k : {reinterpret_cast<const void*>(k_prolong_mfma<1>), reinterpret_cast<const void*>(k_prolong_mfma<2>),
                           reinterpret_cast<const void*>(k_prolong_mfma<4>)}) {
-      const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+      const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, most);
       if (e != hipSuccess) return e;
     }
-  }
+    return hipSuccess;
+  }();
+  if (shm > 65536 && raised != hipSuccess) return raised;
   const dim3 grid(ngroups, (q + 63) / 64);
   if (q <= 16)
     hipLaunchKernelGGL(k_prolong_mfma<1>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u, active);

@@ -235,11 +235,12 @@ hipError_t launch_leaf_factor(const OpDev* ops, const BoxDev* leaves, int nleaf,
   }
   if (max_ny > 256) return hipErrorInvalidValue;
   const size_t shm = factor_shm(max_ny);
-  if (shm > 65536) {
-    hipError_t a = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_leaf_factor),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-    if (a != hipSuccess) return a;
-  }
+  // the limit is raised once, to what the widest leaf needs: setting it per launch
+  // would let a concurrent set-up (another thread) lower it between another
+  // launch's setting and that launch
+  static const hipError_t raised = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_leaf_factor), hipFuncAttributeMaxDynamicSharedMemorySize, (int)factor_shm(256));
+  if (shm > 65536 && raised != hipSuccess) return raised;
   hipLaunchKernelGGL(k_leaf_factor, dim3(2 * count), dim3(TBF), shm, s, ops, leaves, lidx, 0, G, info);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -92,6 +92,7 @@ void* acquire(size_t bytes, hipStream_t stream) {
       if (b.stream != stream) (void)hipEventSynchronize(b.done);
       (void)hipEventDestroy(b.done);
     }
+    (void)hipGetLastError();
     return b.p;
   }
   void* p = nullptr;
@@ -107,18 +108,19 @@ void* acquire(size_t bytes, hipStream_t stream) {
   return p;
 }
 
-void release(void* p, size_t bytes, hipStream_t stream) {
+void release(void* p, size_t bytes, hipStream_t stream, bool idle) {
   if (!p) return;
   const size_t sc = size_class(bytes);
   std::lock_guard<std::mutex> lk(mu);
   int id = 0;
   Device& d = device(id);
-  Block b{p, sc, stream, nullptr};
-  if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-      hipEventRecord(b.done, stream) != hipSuccess) {
+  Block b{p, sc, idle ? nullptr : stream, nullptr};
+  if (!idle && (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
+                hipEventRecord(b.done, stream) != hipSuccess)) {
     (void)hipGetLastError();
     if (b.done) (void)hipEventDestroy(b.done);
     b.done = nullptr;
+    b.stream = nullptr;
     (void)hipStreamSynchronize(stream);
   }
   d.free.emplace(sc, b);
@@ -130,6 +132,23 @@ void release(void* p, size_t bytes, hipStream_t stream) {
     destroy(last->second);
     d.free.erase(last);
   }
+  (void)hipGetLastError();
+}
+
+void forget_stream(hipStream_t stream) {
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto& dv : devices)
+    for (auto& kv : dv.second.free) {
+      Block& b = kv.second;
+      if (b.stream != stream) continue;
+      if (b.done) {
+        (void)hipEventSynchronize(b.done);
+        (void)hipEventDestroy(b.done);
+        b.done = nullptr;
+      }
+      b.stream = nullptr;
+    }
+  (void)hipGetLastError();
 }
 
 size_t trim() {

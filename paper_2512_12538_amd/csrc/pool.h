@@ -6,7 +6,9 @@
 // back on release; a block is reused for a request of the same rounded size
 // class.  A block released on stream s carries an event recorded on s at the
 // release: a later request on the same stream reuses it at once (stream
-// order), a request on another stream first waits for that event.  Cached
+// order), a request on another stream first waits for that event.  The
+// functions ignore HIP errors of their own calls and leave none in the
+// thread's last-error slot.  Cached
 // bytes are capped (HH_POOL_CAP_GB, default a quarter of the device memory);
 // when hipMalloc fails, the cached blocks of the device are freed and the
 // allocation is retried once.
@@ -26,8 +28,15 @@ size_t size_class(size_t bytes);
 void* acquire(size_t bytes, hipStream_t stream);
 
 // Returns a block obtained from acquire (same byte count); work already
-// enqueued on `stream` may still use it.
-void release(void* p, size_t bytes, hipStream_t stream);
+// enqueued on `stream` may still use it (unless idle: nothing pending on the
+// stream uses the block, so no event is recorded).
+void release(void* p, size_t bytes, hipStream_t stream, bool idle = false);
+
+// Waits for and drops the events recorded on `stream` by earlier releases, so
+// that no cached block refers to the stream any more.  Call it before the
+// stream is destroyed (an event recorded on a destroyed stream must not be
+// waited for).
+void forget_stream(hipStream_t stream);
 
 // Frees every cached block of the current device; returns the bytes freed.
 size_t trim();

@@ -98,6 +98,7 @@ struct hh_server {
   std::vector<std::thread> workers;
   std::vector<hipStream_t> streams;
   long long served = 0, misses = 0, evictions = 0;
+  std::string last_err;  // message of the last failed batch
 
   void worker(int w);
   bool take_batch(std::unique_lock<std::mutex>& lk, std::vector<Request*>& batch, uint64_t& id);
@@ -318,8 +319,17 @@ void hh_server::worker(int w) {
       if (U) devpool::release(U, vb, s);
     }
     const Clock::time_point t_end = Clock::now();
+    std::string msg;
+    if (st != HH_OK) {
+      const char* why = e.ctx ? hh_last_error(e.ctx) : hh_last_error(nullptr);  // set-up failures: this thread's
+      msg = std::string(hh_status_string(st)) + " (operator " + std::to_string(id) + ", " + std::to_string(q) +
+            " rhs): " + why;
+      const hipError_t he = hipGetLastError();
+      if (he != hipSuccess) msg += std::string(" [HIP: ") + hipGetErrorString(he) + "]";
+    }
 
     lk.lock();
+    if (!msg.empty()) last_err = msg;
     if (charged) used -= est_run;
     int col = 0;
     for (Request* r : batch) {
@@ -448,6 +458,14 @@ hh_status hh_server_stats(hh_server* sv, int64_t* served, int64_t* misses, int64
   return HH_OK;
 }
 
+const char* hh_server_last_error(hh_server* sv) {
+  thread_local std::string copy;
+  if (!sv) return "null server";
+  std::lock_guard<std::mutex> lk(sv->mu);
+  copy = sv->last_err;
+  return copy.c_str();
+}
+
 hh_status hh_server_destroy(hh_server* sv) {
   if (!sv) return HH_OK;
   {
@@ -459,7 +477,10 @@ hh_status hh_server_destroy(hh_server* sv) {
   for (std::thread& t : sv->workers) t.join();
   for (auto& kv : sv->cache)
     if (kv.second.ctx) hh_destroy(kv.second.ctx);
-  for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+  for (hipStream_t s : sv->streams) {
+    devpool::forget_stream(s);  // no cached block may keep an event of a destroyed stream
+    (void)hipStreamDestroy(s);
+  }
   delete sv;
   (void)hipGetLastError();  // clean-up ignores errors; leave none behind for the caller's next call
   return HH_OK;
