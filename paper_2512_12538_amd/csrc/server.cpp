@@ -231,6 +231,7 @@ void hh_server::worker(int w) {
     const size_t est_op = hit ? 0 : sp.op_bytes + (sp.setup_bytes > est_run ? sp.setup_bytes - est_run : 0);
     const size_t need = est_op + est_run;
     hh_status st = HH_OK;
+    std::string reason;  // admission failures
     bool charged = false;
     while (used + need > (size_t)o.budget_bytes) {
       // evict the least recently used idle operator
@@ -253,10 +254,12 @@ void hh_server::worker(int w) {
         if (kv.first != id && kv.second.busy) others = true;
       if (!others) {
         st = HH_ENOMEM;  // does not fit even alone
+        reason = "the operator and the batch's work space do not fit in the budget";
         break;
       }
       if (stop) {
         st = HH_ESTATE;
+        reason = "server stopping";
         break;
       }
       cv.wait(lk);  // memory frees when another batch ends
@@ -293,6 +296,7 @@ void hh_server::worker(int w) {
       void* U = devpool::acquire(vb, s);
       if (!F || !U) {
         st = HH_ENOMEM;
+        reason = "no device memory for the batch's right-hand sides";
       } else {
         size_t off = 0;
         for (Request* r : batch) {
@@ -321,7 +325,9 @@ void hh_server::worker(int w) {
     const Clock::time_point t_end = Clock::now();
     std::string msg;
     if (st != HH_OK) {
-      const char* why = e.ctx ? hh_last_error(e.ctx) : hh_last_error(nullptr);  // set-up failures: this thread's
+      const char* why = !reason.empty() ? reason.c_str()
+                        : e.ctx       ? hh_last_error(e.ctx)
+                                      : hh_last_error(nullptr);  // set-up failures: this thread's
       msg = std::string(hh_status_string(st)) + " (operator " + std::to_string(id) + ", " + std::to_string(q) +
             " rhs): " + why;
       const hipError_t he = hipGetLastError();

@@ -354,6 +354,7 @@ def test_widest_supported_leaf_and_the_limit(hh):
     with pytest.raises(hh.HelmddError) as e:
         hh.hh_setup(2, 256, 12.0, hh.decomposition([(2, 1)], [4]))
     assert e.value.status == hh.HH_EUNSUPPORTED
+    assert "wider than 256" in str(e.value)  # the set-up's message outlives its context
 
 
 def test_full_interface_space_is_exact_in_one_step(hh):

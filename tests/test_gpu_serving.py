@@ -74,6 +74,7 @@ def _serve(hh, reqs, workers, one_at_a_time, budget=8 << 30):
                 outs.append(u)
         torch.cuda.synchronize()
         stats = srv.stats()
+        stats["last_error"] = srv.last_error()
     return [o.cpu().numpy() for o in outs], results, stats
 
 
@@ -128,8 +129,21 @@ def test_budget_evicts_idle_operators_and_refuses_oversize(hh):
     assert stats["evictions"] >= 3 and stats["misses"] == 4
     for a, b in zip(ref, outs):
         assert np.array_equal(a, b)
-    _, res, _ = _serve(hh, [(21, 1, 904)], workers=1, one_at_a_time=True, budget=1 << 16)
+    assert stats["last_error"] == ""
+    _, res, stats = _serve(hh, [(21, 1, 904)], workers=1, one_at_a_time=True, budget=1 << 16)
     assert res[0]["status"] == hh.HH_ENOMEM
+    assert stats["last_error"].startswith("HH_ENOMEM (operator 21, 1 rhs)")
+
+
+def test_a_second_server_after_a_closed_one_serves_cleanly(hh):
+    """Device blocks cached from a closed server's streams are reused by a new
+    server without waiting on events of the destroyed streams."""
+    reqs = _requests()
+    first, r1, _ = _serve(hh, reqs, workers=3, one_at_a_time=False)
+    second, r2, st2 = _serve(hh, reqs, workers=3, one_at_a_time=False)
+    assert all(r["status"] == hh.HH_OK for r in r1 + r2) and st2["last_error"] == ""
+    for a, b in zip(first, second):
+        assert np.array_equal(a, b)
 
 
 def test_invalid_requests_are_rejected(hh):
