@@ -1049,10 +1049,9 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   BC(launch_fill_zero(Lv.R, nlev * sizeof(c128), s));
   BC(launch_trace_adjoint(c->d_ops, Lv.d, Lv.nbox, q, Lv.d_rows, Lv.d_seg_ptr, Lv.d_seg_y, Lv.d_adj, d_yoff, Y, Lv.R,
                           s));
-  BC(launch_conj_inplace(Lv.R, nlev, s));
+  // (the trace is written conjugated and the gather conjugates what it reads)
   BT(solve_level(c, level, q, Lv.R, Lv.X));
-  BC(launch_conj_inplace(Lv.X, nlev, s));
-  BC(launch_iface_gather(Lv.d, Lv.nbox, q, Lv.d_if, d_bhoff, Lv.X, BH, 0, s));
+  BC(launch_iface_gather(Lv.d, Lv.nbox, q, Lv.d_if, d_bhoff, Lv.X, BH, 0, 1, s));
   // SVD of B: B^H = Q_B R, R = U_R S V_R^H, V_i = Q_B U_R[:, :r]
   BC(launch_qr(Lv.nbox, d_bm, d_qn, d_bhoff, BH, d_soff, Rs, Wk, s));
   BC(launch_jacobi_svd(Lv.nbox, d_qn, d_soff, Rs, d_soff, Us, d_sig, d_sgoff, s));

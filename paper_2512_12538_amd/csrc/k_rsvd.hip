@@ -41,15 +41,17 @@ __global__ void __launch_bounds__(TB) k_iface_gather(const BoxDev* __restrict__ 
                                                      const int* __restrict__ if_idx,
                                                      const long long* __restrict__ voffs,
                                                      const c128* __restrict__ buf, c128* __restrict__ vals,
-                                                     int use_r) {
+                                                     int use_r, int conj_in) {
   const int box = blockIdx.y / q, col = blockIdx.y % q;
   const BoxDev B = boxes[box];
   const int ncol = use_r ? B.r : B.s;
   if (col >= ncol) return;
   const long long base = B.voff * q + (long long)col * B.n;
   c128* v = vals + voffs[box] + (long long)col * B.m_in;
-  for (int t = blockIdx.x * TB + threadIdx.x; t < B.m_in; t += gridDim.x * TB)
-    v[t] = buf[base + if_idx[B.if_off + t]];
+  for (int t = blockIdx.x * TB + threadIdx.x; t < B.m_in; t += gridDim.x * TB) {
+    const double2 x = buf[base + if_idx[B.if_off + t]];
+    v[t] = conj_in ? cconj(x) : x;
+  }
 }
 
 __device__ __forceinline__ bool owns(const BoxDev& B, int p, int q) {
@@ -86,7 +88,10 @@ __global__ void __launch_bounds__(TB) k_trace(const OpDev* __restrict__ ops, con
   }
 }
 
-// H[box][col][y] = sum over trace rows (j, x) reaching y of conj(A~_j[x, y]) Q[row][col]
+// H[box][col][y] = conj of the sum over trace rows (j, x) reaching y of
+// conj(A~_j[x, y]) Q[row][col], i.e. sum A~_j[x, y] conj(Q[row][col]): the
+// conjugated adjoint trace that the solve of B^H = B_i conj(S_i(conj(.))) takes
+// (the conjugations are exact, so writing it conjugated saves a pass)
 __global__ void __launch_bounds__(TB) k_trace_adjoint(const OpDev* __restrict__ ops, const BoxDev* __restrict__ boxes, int q,
                                                       const int2* __restrict__ rows,
                                                       const int* __restrict__ seg_ptr,
@@ -110,7 +115,7 @@ __global__ void __launch_bounds__(TB) k_trace_adjoint(const OpDev* __restrict__ 
       const double2 c = stencil_coef(ops[Bj.prob], Bj.p0, Bj.p1, Bj.q0, Bj.q1, xp, xq, a.y, a.z);
       acc = cfmac(c, qv[a.x], acc);
     }
-    H[hb + seg_y[s]] = acc;
+    H[hb + seg_y[s]] = cconj(acc);
   }
 }
 
@@ -324,9 +329,10 @@ hipError_t launch_iface_scatter(const BoxDev* boxes, int nbox, int q, const int*
 }
 
 hipError_t launch_iface_gather(const BoxDev* boxes, int nbox, int q, const int* if_idx, const long long* voff,
-                               const c128* buf, c128* vals, int use_r, hipStream_t s) {
+                               const c128* buf, c128* vals, int use_r, int conj_in, hipStream_t s) {
   if (nbox <= 0 || q <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_iface_gather, dim3(4, nbox * q), dim3(TB), 0, s, boxes, q, if_idx, voff, buf, vals, use_r);
+  hipLaunchKernelGGL(k_iface_gather, dim3(4, nbox * q), dim3(TB), 0, s, boxes, q, if_idx, voff, buf, vals, use_r,
+                     conj_in);
   return hipGetLastError();
 }
 

@@ -102,11 +102,6 @@ __global__ void k_fill_zero_bytes(unsigned char* __restrict__ p, long long n) {
   for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) p[i] = 0;
 }
 
-__global__ void k_conj(c128* __restrict__ x, long long n) {
-  for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB)
-    x[i] = cconj(x[i]);
-}
-
 __global__ void k_copy(const c128* __restrict__ x, c128* __restrict__ y, long long n) {
   for (long long i = blockIdx.x * (long long)TB + threadIdx.x; i < n; i += (long long)gridDim.x * TB) y[i] = x[i];
 }
@@ -187,12 +182,6 @@ hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t s) {
   } else {
     hipLaunchKernelGGL(k_fill_zero_bytes, dim3(grid_for(bytes)), dim3(TB), 0, s, (unsigned char*)p, bytes);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_conj_inplace(c128* x, long long n, hipStream_t s) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_conj, dim3(grid_for(n)), dim3(TB), 0, s, x, n);
   return hipGetLastError();
 }
 

@@ -21,7 +21,6 @@ hipError_t launch_gather_children(const BoxDev* child, int nchild, int max_n, co
 hipError_t launch_scatter_owned(const BoxDev* child, int nchild, int max_own, const BoxDev* par, int q,
                                 const c128* cbuf, c128* pbuf, hipStream_t s);
 hipError_t launch_fill_zero(void* p, long long bytes, hipStream_t s);
-hipError_t launch_conj_inplace(c128* x, long long n, hipStream_t s);
 hipError_t launch_copy(const c128* x, c128* y, long long n, hipStream_t s);
 // y[col] += x[col] for the columns with active[col] != 0 (all if active is null); columns of length n
 hipError_t launch_add_masked(const c128* x, c128* y, long long n, int q, const int* active, hipStream_t s);
@@ -61,12 +60,13 @@ hipError_t launch_leaf_solve(const OpDev* ops, const BoxDev* leaves, const int* 
 // buf[box][c][iface[t]] = vals[voff[box] + c*m_in + t] for c < (use_r ? r : s); buf pre-zeroed
 hipError_t launch_iface_scatter(const BoxDev* boxes, int nbox, int q, const int* if_idx, const long long* voff,
                                 const c128* vals, int use_r, c128* buf, hipStream_t s);
+// vals[voff[box] + c*m_in + t] = buf[box][c][iface[t]] (conjugated with conj_in)
 hipError_t launch_iface_gather(const BoxDev* boxes, int nbox, int q, const int* if_idx, const long long* voff,
-                               const c128* buf, c128* vals, int use_r, hipStream_t s);
+                               const c128* buf, c128* vals, int use_r, int conj_in, hipStream_t s);
 // Y[yoff[box] + c*tr_cnt + row] = (A~_j R_j P_i X)[x_row]
 hipError_t launch_trace(const OpDev* ops, const BoxDev* boxes, int nbox, int q, const int2* rows,
                         const long long* yoff, const c128* X, c128* Y, hipStream_t s);
-// H[box][c][y] = sum_rows conj(A~_j[x, y]) Q[row][c]; H pre-zeroed
+// H[box][c][y] = conj(sum_rows conj(A~_j[x, y]) Q[row][c]); H pre-zeroed
 hipError_t launch_trace_adjoint(const OpDev* ops, const BoxDev* boxes, int nbox, int q, const int2* rows,
                                 const int* seg_ptr, const int* seg_y, const int4* adj, const long long* yoff,
                                 const c128* Qm, c128* H, hipStream_t s);
