@@ -1054,7 +1054,7 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
   BC(launch_iface_gather(Lv.d, Lv.nbox, q, Lv.d_if, d_bhoff, Lv.X, BH, 0, 1, s));
   // SVD of B: B^H = Q_B R, R = U_R S V_R^H, V_i = Q_B U_R[:, :r]
   BC(launch_qr(Lv.nbox, d_bm, d_qn, d_bhoff, BH, d_soff, Rs, Wk, s));
-  BC(launch_jacobi_svd(Lv.nbox, d_qn, d_soff, Rs, d_soff, Us, d_sig, d_sgoff, s));
+  BC(launch_jacobi_svd(Lv.nbox, d_qn, smax, d_soff, Rs, d_soff, Us, d_sig, d_sgoff, s));
   BC(launch_small_gemm(Lv.nbox, max_mr, d_bm, d_qn, d_rr, d_bhoff, BH, d_soff, Us, d_voff, V, s));
   // C_i = P_i S_i(B_i^T V_i)
   BC(launch_fill_zero(Lv.R, (long long)Lv.total * rmax * sizeof(c128), s));

@@ -15,10 +15,38 @@ constexpr int TB = 256;
 constexpr int TBS = 1024;  // the small dense factorisations: one item (column, column pair) per wave
 constexpr int WAVE = 64;
 
+// Sum over the 64 lanes, returned in every lane, without LDS: DPP within each
+// row of 16 (lane ^ 1, lane ^ 2, rotations by 4 and 8), then the gfx950
+// permlane16 / permlane32 swaps across rows and halves; the lanes add in
+// different orders, so the first lane's sum is broadcast and every lane holds
+// the same bits.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-  return v;
+  v += dpp<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp<0x124>(v);  // row_ror:4
+  v += dpp<0x128>(v);  // row_ror:8
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false,
+                                                     false);
+    v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false,
+                                                     false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false,
+                                                     false);
+    v = __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+  }
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
 }
 __device__ __forceinline__ double2 wave_sum(double2 v) { return mk(wave_sum(v.x), wave_sum(v.y)); }
 
@@ -200,13 +228,22 @@ __global__ void __launch_bounds__(TBS) k_qr(const int* __restrict__ ms, const in
 // One-sided (Hestenes) Jacobi on the columns of R (n x n), round-robin pair
 // order, one wave per pair.  Output: U[:, t] = columns of R J normalised and
 // sorted by decreasing norm (the left singular vectors of R), sigma sorted.
+// INLDS: R is copied to shared memory (dynamic, n_max^2 entries) and rotated
+// there; R in memory is left as it was.
+template <bool INLDS>
 __global__ void __launch_bounds__(TBS) k_jacobi(const int* __restrict__ ns, const long long* __restrict__ roff,
                                                c128* __restrict__ Rall, const long long* __restrict__ uoff,
                                                c128* __restrict__ Uall, double* __restrict__ sig,
                                                const long long* __restrict__ soff) {
   const int pb = blockIdx.x;
   const int n = ns[pb];
+  extern __shared__ double2 rlds[];
   c128* R = Rall + roff[pb];
+  if constexpr (INLDS) {
+    for (int e = threadIdx.x; e < n * n; e += TBS) rlds[e] = R[e];
+    __syncthreads();
+    R = rlds;
+  }
   c128* U = Uall + uoff[pb];
   double* sg = sig + soff[pb];
   const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE, nw = TBS / WAVE;
@@ -359,10 +396,26 @@ hipError_t launch_qr(int nprob, const int* m, const int* n, const long long* aof
   return hipGetLastError();
 }
 
-hipError_t launch_jacobi_svd(int nprob, const int* n, const long long* roff, c128* R, const long long* uoff,
+namespace {
+constexpr int kJacobiLds = 96;  // 96^2 complex128 = 144 KiB of shared memory
+// raised once, to the largest matrix kept in shared memory (a per-call setting
+// could be lowered by a concurrent caller before another's launch)
+hipError_t jacobi_lds_limit() {
+  static const hipError_t raised = hipFuncSetAttribute(reinterpret_cast<const void*>(k_jacobi<true>),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)(sizeof(double2) * kJacobiLds * kJacobiLds));
+  return raised;
+}
+}  // namespace
+
+hipError_t launch_jacobi_svd(int nprob, const int* n, int nmax, const long long* roff, c128* R, const long long* uoff,
                              c128* U, double* sigma, const long long* soff, hipStream_t s) {
   if (nprob <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_jacobi, dim3(nprob), dim3(TBS), 0, s, n, roff, R, uoff, U, sigma, soff);
+  const size_t shm = sizeof(double2) * (size_t)nmax * nmax;
+  if (nmax <= kJacobiLds && (shm <= 65536 || jacobi_lds_limit() == hipSuccess))
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(nprob), dim3(TBS), shm, s, n, roff, R, uoff, U, sigma, soff);
+  else
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(nprob), dim3(TBS), 0, s, n, roff, R, uoff, U, sigma, soff);
   return hipGetLastError();
 }
 

@@ -73,9 +73,10 @@ hipError_t launch_trace_adjoint(const OpDev* ops, const BoxDev* boxes, int nbox,
 // Batched Householder QR: A[b] (m_b x n_b col-major) -> explicit Q in place, R (n_b x n_b); n_b <= 128
 hipError_t launch_qr(int nprob, const int* m, const int* n, const long long* aoff, c128* A, const long long* roff,
                      c128* R, c128* work, hipStream_t s);
-// One-sided Jacobi SVD of R[b] (n_b x n_b, n_b <= 128): U sorted by decreasing singular value, sigma
-hipError_t launch_jacobi_svd(int nprob, const int* n, const long long* roff, c128* R, const long long* uoff,
-                             c128* U, double* sigma, const long long* soff, hipStream_t s);
+// One-sided Jacobi SVD of R[b] (n_b x n_b, n_b <= nmax <= 128): U sorted by decreasing singular value,
+// sigma; the rotations run in shared memory when nmax <= 96 (R left as it was), else on R in place
+hipError_t launch_jacobi_svd(int nprob, const int* n, int nmax, const long long* roff, c128* R,
+                             const long long* uoff, c128* U, double* sigma, const long long* soff, hipStream_t s);
 // V[b] (m_b x r_b) = Q[b] (m_b x n_b) * U[b][:, :r_b]
 hipError_t launch_small_gemm(int nprob, int max_mr, const int* m, const int* n, const int* r, const long long* qoff,
                              const c128* Q, const long long* uoff, const c128* U, const long long* voff, c128* V,
