@@ -317,7 +317,7 @@ def serving(hh, torch, precision, seconds, rate, drain=30.0, seed=11):
                                  torch.randn((4, n), device="cuda", dtype=torch.float64, generator=g)) / np.sqrt(2.0)
     torch.cuda.synchronize()
     results = [None] * len(sched)
-    srv = hh.Server(200 * 10 ** 9, workers=4, max_batch_rhs=32, precision=precision, gmres_restart=100)
+    srv = hh.Server(200 * 10 ** 9, workers=12, max_batch_rhs=32, precision=precision, gmres_restart=100)
     tickets = [None] * len(sched)
     t0 = time.perf_counter()
     deadline = t0 + seconds + drain
@@ -595,7 +595,7 @@ def main():
         out["serving"] = {
             "stream": f"Poisson arrivals for {args.serving_seconds:g} s (then {args.serving_drain:g} s to drain); "
                       "sides 128/256/512/1024 (p .4/.3/.2/.1), k = side/6.4, 1-4 rhs, 70% operator reuse, 200 GB "
-                      "budget, 4 workers, batches <= 32 rhs, GMRES(100) to 1e-8; latency = arrival to result on the "
+                      "budget, 12 workers, batches <= 32 rhs, GMRES(100) to 1e-8; latency = arrival to result on the "
                       "host, requests unfinished at the deadline count as infinitely late",
         }
         for rate in [args.serving_rate] + ([args.serving_rate_low] if args.serving_rate_low > 0 else []):
