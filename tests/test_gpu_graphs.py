@@ -115,3 +115,50 @@ def test_graphs_follow_a_rebuilt_coarse_space(hh):
     finally:
         hh.hh_destroy(eager)
         hh.hh_destroy(graph)
+
+
+def test_concurrent_contexts_on_two_threads_match_sequential(hh):
+    """Two host threads, each with its own stream, set up, build and solve
+    concurrently (the benchmark's lanes): every result equals the one computed
+    alone, bit for bit, and the cached device blocks pass between the streams
+    safely."""
+    import threading
+
+    import torch
+
+    f = W.white_rhs((N + 1) ** 2, 41, 4)
+
+    def run(stream, out, k):
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                ctx = _ctx(hh, stream)
+                try:
+                    out.append(_solve(hh, ctx, f))
+                finally:
+                    hh.hh_destroy(ctx)
+        out.append(k)
+
+    s0 = torch.cuda.Stream()
+    alone = []
+    run(s0, alone, "alone")
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [[], []]
+    errors = []
+
+    def guarded(i):
+        try:
+            run(streams[i], outs[i], i)
+        except BaseException as e:  # noqa: BLE001 - re-raised below
+            errors.append(e)
+
+    threads = [threading.Thread(target=guarded, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errors, errors
+    u_ref, it_ref = alone[0]
+    for out in outs:
+        assert len(out) == 4
+        for u, it in out[:3]:
+            assert it == it_ref and np.array_equal(u, u_ref)
