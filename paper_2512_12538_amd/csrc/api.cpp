@@ -231,7 +231,13 @@ template <typename F>
 hh_status group_leaves(hh_ctx* c, const Level& L, F key, std::vector<LeafGroup>& groups, int** d_order) {
   std::vector<int> idx(L.nbox);
   for (int i = 0; i < L.nbox; ++i) idx[i] = i;
-  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return key(L.hb[a].ny) < key(L.hb[b].ny); });
+  // by group, and within a group the largest leaves (longest line chains) first,
+  // so that the critical chains start at once and the short ones fill in behind
+  auto size = [&](int i) { return (long long)L.hb[i].nx * L.hb[i].ny * L.hb[i].ny; };
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+    const int ka = key(L.hb[a].ny), kb = key(L.hb[b].ny);
+    return ka != kb ? ka < kb : size(a) > size(b);
+  });
   groups.clear();
   for (int t = 0; t < L.nbox; ++t) {
     const int k = key(L.hb[idx[t]].ny);
