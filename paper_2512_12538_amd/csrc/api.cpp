@@ -7,11 +7,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "../../include/helmdd.h"
@@ -50,8 +53,6 @@ struct Level {
   // --- this level's boxes as children of a coarse space (built by build_coarse(level))
   bool built = false;
   int rank = 0, rmax = 0, smax = 0;
-  std::vector<std::vector<TraceRow>> rows;
-  std::vector<std::vector<AdjEntry>> adj;
   bool tables = false;
   int2* d_rows = nullptr;
   int* d_seg_ptr = nullptr;
@@ -225,6 +226,34 @@ hh_status sync(hh_ctx* c) {
 }
 
 hh_status push_boxes(hh_ctx* c, Level& L) { return upload(c, &L.d, L.hb); }
+
+// Runs fn(i) for i in [0, n) on up to 8 host threads (on the calling thread
+// alone for small n); false when a worker ran out of host memory.
+template <typename F>
+bool parallel_for(int n, F fn) {
+  const long long hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = (int)std::min<long long>({8LL, hw, (n + 63LL) / 64});
+  std::atomic<int> next{0};
+  std::atomic<bool> ok{true};
+  auto work = [&]() {
+    try {
+      for (int i; ok.load(std::memory_order_relaxed) && (i = next.fetch_add(1)) < n;) fn(i);
+    } catch (const std::bad_alloc&) {
+      ok = false;
+    }
+  };
+  std::vector<std::thread> th;
+  for (int t = 1; t < nt; ++t) {
+    try {
+      th.emplace_back(work);
+    } catch (const std::system_error&) {
+      break;  // fewer threads: the calling thread takes what is left
+    }
+  }
+  work();
+  for (std::thread& t : th) t.join();
+  return ok.load();
+}
 
 // Groups the leaves by key(ny) (ascending key, leaves ascending within a group).
 template <typename F>
@@ -869,32 +898,57 @@ hh_status hh_build_coarse(hh_ctx* c, int32_t level, int32_t rank, int32_t oversa
     Lv.built = true;
     return HH_OK;
   }
-  // trace tables (geometry only; cached)
+  // trace tables (geometry only; cached).  Every box's tables are independent:
+  // they are built on host threads, then packed at offsets from a prefix sum.
   if (!Lv.tables) {
-    Lv.rows.resize(Lv.nbox);
-    Lv.adj.resize(Lv.nbox);
-    for (int i = 0; i < Lv.nbox; ++i) trace_tables(c->geo, level, i, Lv.rows[i], Lv.adj[i]);
-    std::vector<int2> rows;
-    std::vector<int> seg_ptr, seg_y;
-    std::vector<int4> adj;
+    std::vector<std::vector<TraceRow>> trows(Lv.nbox);
+    std::vector<std::vector<AdjEntry>> tadj(Lv.nbox);
+    std::vector<int> nseg(Lv.nbox, 0);
+    if (!parallel_for(Lv.nbox, [&](int i) {
+          trace_tables(c->geo, level, i, trows[i], tadj[i]);
+          int k = 0, prev = -1;
+          for (const AdjEntry& e : tadj[i])
+            if (e.yl != prev) {
+              ++k;
+              prev = e.yl;
+            }
+          nseg[i] = k;
+        }))
+      return fail(c, HH_ENOMEM, "out of host memory for the interface-map tables");
+    long long nr = 0, ns = 0, na = 0;
+    std::vector<long long> aoff(Lv.nbox);
     for (int i = 0; i < Lv.nbox; ++i) {
-      Lv.hb[i].tr_off = (int)rows.size();
-      Lv.hb[i].tr_cnt = (int)Lv.rows[i].size();
-      Lv.max_tr = std::max(Lv.max_tr, Lv.hb[i].tr_cnt);
-      for (const TraceRow& t : Lv.rows[i]) rows.push_back(make_int2(t.j, t.xl));
-      Lv.hb[i].adj_off = (int)seg_y.size();
-      int prev = -1;
-      for (const AdjEntry& e : Lv.adj[i]) {
+      BoxDev& b = Lv.hb[i];
+      b.tr_off = (int)nr;
+      b.tr_cnt = (int)trows[i].size();
+      b.adj_off = (int)ns;
+      b.adj_cnt = nseg[i];
+      Lv.max_tr = std::max(Lv.max_tr, b.tr_cnt);
+      aoff[i] = na;
+      nr += b.tr_cnt;
+      ns += nseg[i];
+      na += (long long)tadj[i].size();
+    }
+    if (na >= (1LL << 31) || nr >= (1LL << 31)) return fail(c, HH_EUNSUPPORTED, "interface-map tables too large");
+    std::vector<int2> rows(nr);
+    std::vector<int> seg_ptr(ns + 1), seg_y(ns);
+    std::vector<int4> adj(na);
+    parallel_for(Lv.nbox, [&](int i) {
+      const BoxDev& b = Lv.hb[i];
+      for (int t = 0; t < b.tr_cnt; ++t) rows[b.tr_off + t] = make_int2(trows[i][t].j, trows[i][t].xl);
+      long long a = aoff[i];
+      int sg = b.adj_off, prev = -1;
+      for (const AdjEntry& e : tadj[i]) {
         if (e.yl != prev) {
-          seg_ptr.push_back((int)adj.size());
-          seg_y.push_back(e.yl);
+          seg_ptr[sg] = (int)a;
+          seg_y[sg] = e.yl;
+          ++sg;
           prev = e.yl;
         }
-        adj.push_back(make_int4(e.row, e.dp, e.dq, 0));
+        adj[a++] = make_int4(e.row, e.dp, e.dq, 0);
       }
-      Lv.hb[i].adj_cnt = (int)seg_y.size() - Lv.hb[i].adj_off;
-    }
-    seg_ptr.push_back((int)adj.size());
+    });
+    seg_ptr[ns] = (int)na;
     HH_TRY(upload(c, &Lv.d_rows, rows));
     HH_TRY(upload(c, &Lv.d_seg_ptr, seg_ptr));
     HH_TRY(upload(c, &Lv.d_seg_y, seg_y));

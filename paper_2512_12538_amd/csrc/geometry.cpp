@@ -75,11 +75,17 @@ std::string build_geometry(int dim, int n_cells, int levels, const int (*m)[2], 
       const bool lo_x = c.p0 > par.p0, hi_x = c.p1 < par.p1;
       const bool lo_y = dim == 2 && c.q0 > par.q0, hi_y = dim == 2 && c.q1 < par.q1;
       c.n_if = (int)lo_x + (int)hi_x + (int)lo_y + (int)hi_y;
-      for (int p = c.p0; p <= c.p1; ++p)
-        for (int q = c.q0; q <= c.q1; ++q) {
-          bool on = (lo_x && p == c.p0) || (hi_x && p == c.p1) || (lo_y && q == c.q0) || (hi_y && q == c.q1);
-          if (on) c.iface.push_back(c.local(p, q));
+      // node rows on an x side are interface nodes whole; the other rows hold
+      // at most their two y ends (a 2D box has ny >= 2, so the ends differ)
+      c.iface.reserve(2 * (c.nx() + c.ny()));
+      for (int p = c.p0; p <= c.p1; ++p) {
+        if ((lo_x && p == c.p0) || (hi_x && p == c.p1)) {
+          for (int q = c.q0; q <= c.q1; ++q) c.iface.push_back(c.local(p, q));
+        } else {
+          if (lo_y) c.iface.push_back(c.local(p, c.q0));
+          if (hi_y) c.iface.push_back(c.local(p, c.q1));
         }
+      }
       for (int o : par.children) {
         if (o == c.index) continue;
         const HBox& d = boxes[o];
