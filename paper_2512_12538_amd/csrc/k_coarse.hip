@@ -531,80 +531,93 @@ __global__ void __launch_bounds__(TB) k_coarse_gemm(const ParentDev* __restrict_
 
 // u[par][c][owned nodes of child] += C_child y: computed transposed,
 // (y^T C^T)[c][e], so that a wave's D tile spans 16 consecutive owned nodes.
-// Wave: 16 nodes x 64 right-hand sides (four tiles); inner dimension r.  The
-// work-group's y block (r x 64) is staged in LDS once; each lane loads its C
-// column slice (KU steps) before the products.
+// Wave: 16 nodes x 16 NTL right-hand sides (NTL tiles); inner dimension r.
+// The box's y block (r x 16 NTL) is staged in LDS once per box; each lane
+// loads its C column slice (KU steps) before the products.
 constexpr int PR_MAXR = 128;
 
-// Work-group: (child, group of 64 owned nodes) = groups[blockIdx.x] (the
-// groups of every child with a coarse space, numbered consecutively) and 64
-// right-hand sides (blockIdx.y); NTL tiles of 16 right-hand sides per wave
-// (fewer when q is small; an output's arithmetic is the same for any NTL).
-// With active flags a work-group none of whose right-hand sides is active
-// returns before any access.
-template <int NTL>
+// Work-group: PGN consecutive entries of the group list (child, group of 64
+// owned nodes), the groups of every child with a coarse space numbered
+// consecutively, and 16 NTL right-hand sides from 64 blockIdx.y.  NTL tiles of
+// 16 right-hand sides per wave (fewer when q is small; an output's arithmetic
+// is the same for any NTL and PGN).  Several groups per work-group (few
+// right-hand sides) spread the set-up of a work-group (box records, y staging)
+// over more nodes and keep more work-groups resident in the LDS.  With active
+// flags a box none of whose right-hand sides is active is skipped before any
+// access.  Every branch around a barrier depends on the work-group's group
+// entries only (uniform).
+template <int NTL, int PGN>
 __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
                                                      const ParentDev* __restrict__ pd,
-                                                     const int2* __restrict__ groups, int q,
+                                                     const int2* __restrict__ groups, int ngroups, int q,
                                                      const c128* __restrict__ C, const c128* __restrict__ y,
                                                      c128* __restrict__ u, const int* __restrict__ active) {
-  const int2 bg = groups[blockIdx.x];
-  const int box = bg.x;
-  const BoxDev B = child[box];
-  const int g0 = bg.y * (TB / 64) * 16;
-  if (B.r == 0 || g0 >= B.n_own) return;
-  const int c0 = blockIdx.y * 64;
-  if (active) {
-    bool any = false;
-    for (int cc = c0; cc < q && cc < c0 + 64; ++cc) any = any || active[B.prob * q + cc];
-    if (!any) return;
-  }
-  const BoxDev P = par[B.parent];
-  const ParentDev D = pd[B.parent];
-  extern __shared__ double2 ys[];  // ys[c][a], 64 x (r + 1)
-  const int rs = B.r + 1;
-  for (int idx = threadIdx.x; idx < 64 * B.r; idx += TB) {
-    const int cl = idx / B.r, a = idx - cl * B.r;
-    const int c = c0 + cl;
-    ys[cl * rs + a] = c < q ? y[D.yoff * q + (long long)c * D.n_c + B.cidx + a] : mk(0.0, 0.0);
-  }
-  __syncthreads();
+  extern __shared__ double2 ys[];  // ys[c][a], 16 NTL x (r + 1)
   const int lane = threadIdx.x & 63, m = lane & 15, kk = lane >> 4;
-  const int e0 = g0 + (threadIdx.x >> 6) * 16;
-  if (e0 >= B.n_own) return;
-  const c128* Cb = C + B.coff;
-  const int en = e0 + m;
-  d4 re[NTL], im[NTL];
-#pragma unroll
-  for (int t = 0; t < NTL; ++t) re[t] = im[t] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < B.r; k0 += 4 * KU) {
-    double2 cv[KU];
-#pragma unroll
-    for (int uu = 0; uu < KU; ++uu) {
-      const int a = k0 + 4 * uu + kk;
-      cv[uu] = (a < B.r && en < B.n_own) ? Cb[(long long)a * B.n_own + en] : mk(0.0, 0.0);
+  const int c0 = blockIdx.y * 64;
+  int staged = -1;
+  for (int sub = 0; sub < PGN; ++sub) {
+    const int gi = blockIdx.x * PGN + sub;
+    if (gi >= ngroups) break;
+    const int2 bg = groups[gi];
+    const int box = bg.x;
+    const BoxDev B = child[box];
+    const int g0 = bg.y * (TB / 64) * 16;
+    if (B.r == 0 || g0 >= B.n_own) continue;
+    if (active) {
+      bool any = false;
+      for (int cc = c0; cc < q && cc < c0 + 16 * NTL; ++cc) any = any || active[B.prob * q + cc];
+      if (!any) continue;
     }
+    const BoxDev P = par[B.parent];
+    const int rs = B.r + 1;
+    if (box != staged) {
+      const ParentDev D = pd[B.parent];
+      __syncthreads();  // the previous box's products have read their y block
+      for (int idx = threadIdx.x; idx < 16 * NTL * B.r; idx += TB) {
+        const int cl = idx / B.r, a = idx - cl * B.r;
+        const int c = c0 + cl;
+        ys[cl * rs + a] = c < q ? y[D.yoff * q + (long long)c * D.n_c + B.cidx + a] : mk(0.0, 0.0);
+      }
+      __syncthreads();
+      staged = box;
+    }
+    const int e0 = g0 + (threadIdx.x >> 6) * 16;
+    if (e0 >= B.n_own) continue;
+    const c128* Cb = C + B.coff;
+    const int en = e0 + m;
+    d4 re[NTL], im[NTL];
 #pragma unroll
-    for (int uu = 0; uu < KU; ++uu) {
-      if (k0 + 4 * uu >= B.r) break;  // steps past this box's rank skipped
-      const int a = k0 + 4 * uu + kk;
+    for (int t = 0; t < NTL; ++t) re[t] = im[t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < B.r; k0 += 4 * KU) {
+      double2 cv[KU];
 #pragma unroll
-      for (int t = 0; t < NTL; ++t) {
-        const double2 yv = a < B.r ? ys[(16 * t + m) * rs + a] : mk(0.0, 0.0);
-        cmfma(yv, cv[uu], re[t], im[t]);
+      for (int uu = 0; uu < KU; ++uu) {
+        const int a = k0 + 4 * uu + kk;
+        cv[uu] = (a < B.r && en < B.n_own) ? Cb[(long long)a * B.n_own + en] : mk(0.0, 0.0);
+      }
+#pragma unroll
+      for (int uu = 0; uu < KU; ++uu) {
+        if (k0 + 4 * uu >= B.r) break;  // steps past this box's rank skipped
+        const int a = k0 + 4 * uu + kk;
+#pragma unroll
+        for (int t = 0; t < NTL; ++t) {
+          const double2 yv = a < B.r ? ys[(16 * t + m) * rs + a] : mk(0.0, 0.0);
+          cmfma(yv, cv[uu], re[t], im[t]);
+        }
       }
     }
-  }
-  const int e = e0 + (lane & 15);
-  if (e < B.n_own) {
-    c128* ub = u + P.voff * q + owned_to_parent(B, P, e);
+    const int e = e0 + (lane & 15);
+    if (e < B.n_own) {
+      c128* ub = u + P.voff * q + owned_to_parent(B, P, e);
 #pragma unroll
-    for (int t = 0; t < NTL; ++t)
+      for (int t = 0; t < NTL; ++t)
 #pragma unroll
-      for (int sl = 0; sl < 4; ++sl) {
-        const int c = c0 + 16 * t + 4 * sl + (lane >> 4);
-        if (c < q) ub[(long long)c * P.n] = cadd(ub[(long long)c * P.n], mk(re[t][sl], im[t][sl]));
-      }
+        for (int sl = 0; sl < 4; ++sl) {
+          const int c = c0 + 16 * t + 4 * sl + (lane >> 4);
+          if (c < q) ub[(long long)c * P.n] = cadd(ub[(long long)c * P.n], mk(re[t][sl], im[t][sl]));
+        }
+    }
   }
 }
 
@@ -739,24 +752,31 @@ hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ng
                                  const int* active, hipStream_t s) {
   if (ngroups <= 0 || q <= 0) return hipSuccess;
   if (rmax > PR_MAXR) return hipErrorInvalidValue;
-  const size_t shm = sizeof(double2) * 64 * (size_t)(rmax + 1);
+  const int ntl = q <= 16 ? 1 : q <= 32 ? 2 : 4;
+  const size_t shm = sizeof(double2) * 16 * ntl * (size_t)(rmax + 1);
   // raised once, to the largest rank (see launch_gj_inverse)
   static const hipError_t raised = [] {
     const int most = (int)(sizeof(double2) * 64 * (PR_MAXR + 1));
-    for (const void* k : {reinterpret_cast<const void*>(k_prolong_mfma<1>), reinterpret_cast<const void*>(k_prolong_mfma<2>),
-                          reinterpret_cast<const void*>(k_prolong_mfma<4>)}) {
+    for (const void* k : {reinterpret_cast<const void*>(k_prolong_mfma<1, 4>),
+                          reinterpret_cast<const void*>(k_prolong_mfma<2, 4>),
+                          reinterpret_cast<const void*>(k_prolong_mfma<4, 1>)}) {
       const hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, most);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }();
   if (shm > 65536 && raised != hipSuccess) return raised;
-  const dim3 grid(ngroups, (q + 63) / 64);
-  if (q <= 16)
-    hipLaunchKernelGGL(k_prolong_mfma<1>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u, active);
-  else if (q <= 32)
-    hipLaunchKernelGGL(k_prolong_mfma<2>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u, active);
+  // few right-hand sides: four node groups per work-group; 64: one (enough work-groups to fill the chip)
+  const int pgn = ntl == 4 ? 1 : 4;
+  const dim3 grid((ngroups + pgn - 1) / pgn, (q + 63) / 64);
+  if (ntl == 1)
+    hipLaunchKernelGGL((k_prolong_mfma<1, 4>), grid, dim3(TB), shm, s, child, par, pd, groups, ngroups, q, C, y, u,
+                       active);
+  else if (ntl == 2)
+    hipLaunchKernelGGL((k_prolong_mfma<2, 4>), grid, dim3(TB), shm, s, child, par, pd, groups, ngroups, q, C, y, u,
+                       active);
   else
-    hipLaunchKernelGGL(k_prolong_mfma<4>, grid, dim3(TB), shm, s, child, par, pd, groups, q, C, y, u, active);
+    hipLaunchKernelGGL((k_prolong_mfma<4, 1>), grid, dim3(TB), shm, s, child, par, pd, groups, ngroups, q, C, y, u,
+                       active);
   return hipGetLastError();
 }
