@@ -468,23 +468,48 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__
   }
 }
 
-// cvec[par][c][cidx + a] = sum over the child's chunks (in order) of part[g][a][c];
-// cbase[child] = its first chunk
-__global__ void __launch_bounds__(TB) k_restrict_sum(const BoxDev* __restrict__ child,
-                                                     const ParentDev* __restrict__ pd, const int* __restrict__ cbase,
-                                                     int rpad, int q, int qpad, const c128* __restrict__ part,
-                                                     c128* __restrict__ cvec) {
+// cvec[par][c][cidx + a] = sum over the child's chunks of part[g][a][c];
+// cbase[child] = its first chunk.  Work-group: 64 outputs (a, c) of one child
+// (lanes) x RS_SEG waves; wave k sums the chunks k, k + RS_SEG, ... in turn,
+// then wave 0 adds the RS_SEG partial sums in wave order.  The order depends on
+// the child's chunk count only (not on q): a box with thousands of chunks is
+// summed by 16 chains in parallel instead of one.
+constexpr int RS_SEG = 16;
+__global__ void __launch_bounds__(64 * RS_SEG) k_restrict_sum(const BoxDev* __restrict__ child,
+                                                              const ParentDev* __restrict__ pd,
+                                                              const int* __restrict__ cbase, int rpad, int q,
+                                                              int qpad, const c128* __restrict__ part,
+                                                              c128* __restrict__ cvec) {
   const int box = blockIdx.y;
   const BoxDev B = child[box];
-  const int idx = blockIdx.x * TB + threadIdx.x;
+  if (blockIdx.x * 64 >= B.r * q) return;  // the same for the whole work-group
+  const int lane = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + lane;
   const int a = idx / q, c = idx - a * q;
-  if (a >= B.r) return;
-  const ParentDev D = pd[B.parent];
+  const bool live = a < B.r;
   const int nch = (B.n_own + RCH - 1) / RCH;
-  const c128* pb = part + (long long)cbase[box] * rpad * qpad + (long long)a * qpad + c;
-  double2 s = mk(0.0, 0.0);
-  for (int ch = 0; ch < nch; ++ch) s = cadd(s, pb[(long long)ch * rpad * qpad]);
-  cvec[D.yoff * q + (long long)c * D.n_c + B.cidx + a] = s;
+  const long long st = (long long)rpad * qpad;
+  double2 acc = mk(0.0, 0.0);
+  if (live) {
+    const c128* pb = part + (long long)cbase[box] * st + (long long)a * qpad + c;
+    int ch = sg;
+    for (; ch + 3 * RS_SEG < nch; ch += 4 * RS_SEG) {
+      const double2 v0 = pb[ch * st], v1 = pb[(ch + RS_SEG) * st], v2 = pb[(ch + 2 * RS_SEG) * st],
+                    v3 = pb[(ch + 3 * RS_SEG) * st];
+      acc = cadd(cadd(cadd(cadd(acc, v0), v1), v2), v3);
+    }
+    for (; ch < nch; ch += RS_SEG) acc = cadd(acc, pb[ch * st]);
+  }
+  __shared__ double2 red[RS_SEG][64];
+  red[sg][lane] = acc;
+  __syncthreads();
+  if (sg == 0 && live) {
+    double2 s = red[0][lane];
+#pragma unroll
+    for (int k = 1; k < RS_SEG; ++k) s = cadd(s, red[k][lane]);
+    const ParentDev D = pd[B.parent];
+    cvec[D.yoff * q + (long long)c * D.n_c + B.cidx + a] = s;
+  }
 }
 
 // y[par][c] = A_c^{-1} cvec[par][c]: one work-group per 16 x 16 output tile
@@ -732,7 +757,7 @@ hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* c
   else
     hipLaunchKernelGGL(k_restrict_mfma<8>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part,
                        active);
-  hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + TB - 1) / TB, nchild), dim3(TB), 0, s, child, pd, cbase,
+  hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + 63) / 64, nchild), dim3(64 * RS_SEG), 0, s, child, pd, cbase,
                      16 * mt, q, ncg * 16, part, cvec);
   return hipGetLastError();
 }

@@ -211,17 +211,38 @@ __global__ void __launch_bounds__(TB) k_dot_partial(int nk, SegDev sg, int S1, c
   }
 }
 
-// out[t] = sum over the chunks of system t % S of partial[blk*nkq + t], in chunk order
-__global__ void k_dot_final(int nkq, int S, const int* __restrict__ nb, const c128* __restrict__ partial,
-                            c128* __restrict__ out, const int* __restrict__ skip) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nkq) return;
-  const int b = t % S;
-  if (skip && !skip[b]) return;
-  const int NB = nb[b];
+// out[t] = sum over the chunks of system t % S of partial[blk*nkq + t].
+// Work-group: 64 outputs (lanes) x DF_SEG waves; wave k sums the chunks k,
+// k + DF_SEG, ... in turn, then wave 0 adds the DF_SEG partial sums in wave
+// order.  The order depends on the system's chunk count only.
+constexpr int DF_SEG = 16;
+__global__ void __launch_bounds__(64 * DF_SEG) k_dot_final(int nkq, int S, const int* __restrict__ nb,
+                                                           const c128* __restrict__ partial, c128* __restrict__ out,
+                                                           const int* __restrict__ skip) {
+  const int lane = threadIdx.x & 63, sg = threadIdx.x >> 6;
+  const int t = blockIdx.x * 64 + lane;
+  const bool live = t < nkq && (!skip || skip[t % S]);
   double2 acc = mk(0.0, 0.0);
-  for (int blk = 0; blk < NB; ++blk) acc = cadd(acc, partial[(long long)blk * nkq + t]);
-  out[t] = acc;
+  if (live) {
+    const int NB = nb[t % S];
+    int blk = sg;
+    for (; blk + 3 * DF_SEG < NB; blk += 4 * DF_SEG) {
+      const double2 v0 = partial[(long long)blk * nkq + t], v1 = partial[(long long)(blk + DF_SEG) * nkq + t],
+                    v2 = partial[(long long)(blk + 2 * DF_SEG) * nkq + t],
+                    v3 = partial[(long long)(blk + 3 * DF_SEG) * nkq + t];
+      acc = cadd(cadd(cadd(cadd(acc, v0), v1), v2), v3);
+    }
+    for (; blk < NB; blk += DF_SEG) acc = cadd(acc, partial[(long long)blk * nkq + t]);
+  }
+  __shared__ double2 red[DF_SEG][64];
+  red[sg][lane] = acc;
+  __syncthreads();
+  if (sg == 0 && live) {
+    double2 r = red[0][lane];
+#pragma unroll
+    for (int k = 1; k < DF_SEG; ++k) r = cadd(r, red[k][lane]);
+    out[t] = r;
+  }
 }
 
 // W[b] -= sum_k V_k[b] h[k*S + b] over one chunk per work-group; optionally the
@@ -451,7 +472,8 @@ hipError_t launch_multidot(int nk, const SegDev& sg, const c128* V, long long vs
   const long long grid = (nlog + NXCD - 1) / NXCD * NXCD;
   hipLaunchKernelGGL(k_dot_partial, dim3((unsigned)grid), dim3(TB), 0, s, nk, sg, nkq, V, vstride, W, partial, wnorm,
                      skip);
-  hipLaunchKernelGGL(k_dot_final, dim3((nkq + 127) / 128), dim3(128), 0, s, nkq, sg.S, sg.nb, partial, out, skip);
+  hipLaunchKernelGGL(k_dot_final, dim3((nkq + 63) / 64), dim3(64 * DF_SEG), 0, s, nkq, sg.S, sg.nb, partial, out,
+                     skip);
   return hipGetLastError();
 }
 
@@ -461,8 +483,8 @@ hipError_t launch_basis_update(int nk, const SegDev& sg, const c128* V, long lon
   hipLaunchKernelGGL(k_basis_update, dim3(sg.G), dim3(TB), 0, s, nk, sg, V, vstride, h, W, nrm2 ? partial : nullptr,
                      skip);
   if (nrm2)
-    hipLaunchKernelGGL(k_dot_final, dim3((sg.S + 127) / 128), dim3(128), 0, s, sg.S, sg.S, sg.nb, partial, nrm2,
-                       skip);
+    hipLaunchKernelGGL(k_dot_final, dim3((sg.S + 63) / 64), dim3(64 * DF_SEG), 0, s, sg.S, sg.S, sg.nb, partial,
+                       nrm2, skip);
   return hipGetLastError();
 }
 
