@@ -394,6 +394,15 @@ __device__ __forceinline__ long long owned_to_parent(const BoxDev& B, const BoxD
 }
 
 constexpr int RCH = 128;  // owned nodes per restrict work-group (split of the inner dimension)
+constexpr int RST = 17;   // LDS row stride (double2) of a staged C column slice of 16 nodes
+
+// LDS written by some lanes of a wave and read by others: a wave's LDS
+// operations complete in issue order, so fences and a compiler barrier suffice
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
 constexpr int KU = 8;     // inner steps whose operands are loaded before their products
 
 // Restriction work items: chunk g = (child, chunk index) of RCH owned nodes,
@@ -492,11 +501,15 @@ __global__ void __launch_bounds__(64 * RS_SEG) k_restrict_sum(const BoxDev* __re
   double2 acc = mk(0.0, 0.0);
   if (live) {
     const c128* pb = part + (long long)cbase[box] * st + (long long)a * qpad + c;
+    // eight loads in flight, added in chunk order
+    constexpr int RU = 8;
     int ch = sg;
-    for (; ch + 3 * RS_SEG < nch; ch += 4 * RS_SEG) {
-      const double2 v0 = pb[ch * st], v1 = pb[(ch + RS_SEG) * st], v2 = pb[(ch + 2 * RS_SEG) * st],
-                    v3 = pb[(ch + 3 * RS_SEG) * st];
-      acc = cadd(cadd(cadd(cadd(acc, v0), v1), v2), v3);
+    for (; ch + (RU - 1) * RS_SEG < nch; ch += RU * RS_SEG) {
+      double2 v[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) v[u] = pb[(ch + u * RS_SEG) * st];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) acc = cadd(acc, v[u]);
     }
     for (; ch < nch; ch += RS_SEG) acc = cadd(acc, pb[ch * st]);
   }
@@ -646,6 +659,163 @@ __global__ void __launch_bounds__(TB) k_prolong_mfma(const BoxDev* __restrict__ 
   }
 }
 
+// Few right-hand sides (q <= RV_MAXQ) and ranks up to 32: the restriction and
+// the prolongation as vector FMA chains.  The matrix-core kernels spend 16
+// right-hand-side columns of work per tile whatever q is; these do q.
+// v_mfma_f64_16x16x4f64 adds its four k terms to the accumulator as a chain of
+// fused multiply-adds in k order (compared bit for bit with exact rational
+// arithmetic on random operands of mixed magnitude), so chains taken in the
+// order of the matrix-core kernels give the same bits: a column's result does
+// not depend on which of the kernels the batch width selects.
+constexpr int RV_MAXQ = 4;
+constexpr int RV_MAXR = 32;
+
+// One wave per restriction chunk (RCH owned nodes): C and t staged through the
+// wave's LDS slice 16 nodes at a time (coalesced loads); lane l accumulates the
+// outputs (a, c) = (l & 31, (l >> 5) + 2 j).  Per output and group of four
+// nodes: re += Cx tx, re += Cy ty, im += Cx ty, im += -Cy tx, each over the
+// four nodes in order (the sequence of cmfma_ca in k_restrict_mfma<2>).
+__global__ void __launch_bounds__(TB) k_restrict_vec(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
+                                                     const int2* __restrict__ chunks, int nitems, int q,
+                                                     const c128* __restrict__ C, const c128* __restrict__ t,
+                                                     c128* __restrict__ part, const int* __restrict__ active) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = blockIdx.x * (TB / 64) + wave;
+  if (g >= nitems) return;
+  const int2 bc = chunks[g];
+  const BoxDev B = child[bc.x];
+  if (active) {
+    bool any = false;
+    for (int cc = 0; cc < q; ++cc) any = any || active[B.prob * q + cc];
+    if (!any) return;
+  }
+  const BoxDev P = par[B.parent];
+  const int e0 = bc.y * RCH;
+  const int e1 = e0 + RCH < B.n_own ? e0 + RCH : B.n_own;
+  const c128* tb = t + P.voff * q;
+  const c128* Cb = C + B.coff;
+  __shared__ double2 cst[TB / 64][RV_MAXR * RST];
+  __shared__ double2 tst[TB / 64][RV_MAXQ * RST];
+  double2* cw = cst[wave];
+  double2* tw = tst[wave];
+  const int a = lane & 31, cl = lane >> 5;
+  double re[2] = {0.0, 0.0}, im[2] = {0.0, 0.0};
+  for (int k0 = e0; k0 < e1; k0 += 16) {
+    const int e = k0 + (lane & 15);
+    double2 cv[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int aa = 4 * i + (lane >> 4);
+      cv[i] = (e < e1 && aa < B.r) ? Cb[(long long)aa * B.n_own + e] : mk(0.0, 0.0);
+    }
+    const int ct = lane >> 4;
+    const double2 tv = (e < e1 && ct < q) ? tb[(long long)ct * P.n + owned_to_parent(B, P, e)] : mk(0.0, 0.0);
+    wave_lds_sync();  // the previous stage's operands have been read
+#pragma unroll
+    for (int i = 0; i < 8; ++i) cw[(4 * i + (lane >> 4)) * RST + (lane & 15)] = cv[i];
+    tw[ct * RST + (lane & 15)] = tv;
+    wave_lds_sync();
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int c = cl + 2 * j;
+      if (c >= q) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double2 cc[4], tt[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          cc[k] = cw[a * RST + 4 * u + k];
+          tt[k] = tw[c * RST + 4 * u + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) re[j] = fma(cc[k].x, tt[k].x, re[j]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) re[j] = fma(cc[k].y, tt[k].y, re[j]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) im[j] = fma(cc[k].x, tt[k].y, im[j]);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) im[j] = fma(-cc[k].y, tt[k].x, im[j]);
+      }
+    }
+  }
+  // the tile layout of k_restrict_mfma<2> with one column group: part[g][a][c], 16 columns
+  c128* pb = part + (long long)g * (2 * 16) * 16;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int c = cl + 2 * j;
+    if (c < q) pb[a * 16 + c] = mk(re[j], im[j]);
+  }
+}
+
+// One wave per group of 64 owned nodes (lane = node), four groups per
+// work-group; the box's y block staged in the wave's LDS slice.  Per output
+// and group of four coarse vectors: re += yx Cx, re += -yy Cy, im += yx Cy,
+// im += yy Cx, each over the four in order (the sequence of cmfma in
+// k_prolong_mfma).
+__global__ void __launch_bounds__(TB) k_prolong_vec(const BoxDev* __restrict__ child, const BoxDev* __restrict__ par,
+                                                    const ParentDev* __restrict__ pd,
+                                                    const int2* __restrict__ groups, int ngroups, int q,
+                                                    const c128* __restrict__ C, const c128* __restrict__ y,
+                                                    c128* __restrict__ u, const int* __restrict__ active) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gi = blockIdx.x * (TB / 64) + wave;
+  if (gi >= ngroups) return;
+  const int2 bg = groups[gi];
+  const BoxDev B = child[bg.x];
+  const int g0 = bg.y * (TB / 64) * 16;
+  if (B.r == 0 || g0 >= B.n_own) return;
+  if (active) {
+    bool any = false;
+    for (int cc = 0; cc < q; ++cc) any = any || active[B.prob * q + cc];
+    if (!any) return;
+  }
+  const BoxDev P = par[B.parent];
+  const ParentDev D = pd[B.parent];
+  __shared__ double2 yst[TB / 64][RV_MAXQ * (RV_MAXR + 1)];
+  double2* yw = yst[wave];
+  constexpr int YR = RV_MAXR + 1;
+  for (int idx = lane; idx < q * B.r; idx += 64) {
+    const int c = idx / B.r, a = idx - c * B.r;
+    yw[c * YR + a] = y[D.yoff * q + (long long)c * D.n_c + B.cidx + a];
+  }
+  wave_lds_sync();
+  const int e = g0 + lane;
+  const bool ve = e < B.n_own;
+  const c128* Cb = C + B.coff;
+  double re[RV_MAXQ], im[RV_MAXQ];
+#pragma unroll
+  for (int c = 0; c < RV_MAXQ; ++c) re[c] = im[c] = 0.0;
+  for (int k0 = 0; k0 < B.r; k0 += 4) {
+    double2 cv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      cv[k] = (k0 + k < B.r && ve) ? Cb[(long long)(k0 + k) * B.n_own + e] : mk(0.0, 0.0);
+#pragma unroll
+    for (int c = 0; c < RV_MAXQ; ++c) {
+      if (c >= q) break;
+      double2 yv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) yv[k] = k0 + k < B.r ? yw[c * YR + k0 + k] : mk(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) re[c] = fma(yv[k].x, cv[k].x, re[c]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) re[c] = fma(-yv[k].y, cv[k].y, re[c]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) im[c] = fma(yv[k].x, cv[k].y, im[c]);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) im[c] = fma(yv[k].y, cv[k].x, im[c]);
+    }
+  }
+  if (ve) {
+    c128* ub = u + P.voff * q + owned_to_parent(B, P, e);
+#pragma unroll
+    for (int c = 0; c < RV_MAXQ; ++c) {
+      if (c >= q) break;
+      ub[(long long)c * P.n] = cadd(ub[(long long)c * P.n], mk(re[c], im[c]));
+    }
+  }
+}
+
 inline int gx(long long n, int cap) {
   long long g = (n + TB - 1) / TB;
   return (int)(g < 1 ? 1 : (g > cap ? cap : g));
@@ -748,7 +918,9 @@ hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* c
   const long long nitems = (long long)nchunks * ncg;
   if (nitems > (1LL << 30)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((nitems + TB / 64 - 1) / (TB / 64)));
-  if (mt == 2)
+  if (mt == 2 && q <= RV_MAXQ)
+    hipLaunchKernelGGL(k_restrict_vec, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, q, C, t, part, active);
+  else if (mt == 2)
     hipLaunchKernelGGL(k_restrict_mfma<2>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part,
                        active);
   else if (mt == 4)
@@ -777,6 +949,11 @@ hipError_t launch_coarse_prolong(const BoxDev* child, const int2* groups, int ng
                                  const int* active, hipStream_t s) {
   if (ngroups <= 0 || q <= 0) return hipSuccess;
   if (rmax > PR_MAXR) return hipErrorInvalidValue;
+  if (q <= RV_MAXQ && rmax <= RV_MAXR) {
+    hipLaunchKernelGGL(k_prolong_vec, dim3((ngroups + TB / 64 - 1) / (TB / 64)), dim3(TB), 0, s, child, par, pd, groups,
+                       ngroups, q, C, y, u, active);
+    return hipGetLastError();
+  }
   const int ntl = q <= 16 ? 1 : q <= 32 ? 2 : 4;
   const size_t shm = sizeof(double2) * 16 * ntl * (size_t)(rmax + 1);
   // raised once, to the largest rank (see launch_gj_inverse)

@@ -236,6 +236,27 @@ def test_batch_invariance(hh):
         hh.hh_destroy(ctx)
 
 
+def test_columns_identical_across_coarse_kernel_paths(hh):
+    """A column's bits do not depend on the batch width where the width picks
+    another coarse restriction/prolongation kernel (vector FMA chains for up to
+    four right-hand sides, matrix cores for more): 20 columns solved together
+    and the first two alone."""
+    from gpu_util import build_both, dev, host
+
+    ctx, S = _case_2d(hh, 48, [(3, 3)], 12.0, 4, 6)
+    try:
+        build_both(hh, ctx, S, rank=4, oversample=6)
+        f = W.smoothed_gaussian_rhs(48, 23, 20)
+        u20 = dev(np.zeros_like(f))
+        info20 = hh.hh_solve(ctx, dev(f), u20, rtol=1e-8, maxit=100)
+        u2 = dev(np.zeros_like(f[:2]))
+        info2 = hh.hh_solve(ctx, dev(f[:2]), u2, rtol=1e-8, maxit=100)
+        assert [i[0] for i in info2] == [i[0] for i in info20[:2]]
+        assert np.array_equal(host(u2), host(u20)[:2])
+    finally:
+        hh.hh_destroy(ctx)
+
+
 def test_hierarchy_two_levels_matches_oracle(hh):
     from gpu_util import build_both, dev, host, rel
 
