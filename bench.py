@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFS = 78.6
 CFG = dict(N=256, k=40.0, m=[(4, 4)], overlap=[4], rank=8, oversample=10, rtol=1e-8, maxit=500, restart=50)
 FAMILY = {0: "k_sweep (leaf block-tridiagonal solve, phase 1 + phase 2)", 1: "k_basis_update (Gram-Schmidt)",
-          2: "k_dot_partial (Gram-Schmidt inner products)"}
+          2: "k_dot_partial (Gram-Schmidt inner products)", 3: "k_apply_box (5-point stencil y = A z)"}
 
 
 def parse():
@@ -238,6 +238,8 @@ def roofline(prof, precision, nrhs, lanes):
                 "families": {FAMILY[k]: {"launches": int(v[0]), "total_ms": round(v[1], 2),
                                          "avg_launch_us": round(1000.0 * v[1] / v[0], 2) if v[0] else None,
                                          "algorithmic_bytes_per_launch": round(v[2] / v[0]) if v[0] else None,
+                                         "hbm_frac": round(v[2] / (v[1] / 1000.0) / 1e9 / HBM_PEAK_GBS, 4)
+                                         if v[0] and v[1] > 0 else None,
                                          "traffic": measured_traffic(k, nrhs, precision, lanes)}
                              for k, v in prof.items()}})
     return out

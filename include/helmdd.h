@@ -197,6 +197,9 @@ hh_status hh_get_basis(hh_ctx* c, int32_t level, int32_t box, int32_t* n_own, in
  *             e = 16 bytes for complex128 factors, 8 for complex64)
  *   family 1  first Gram-Schmidt update W -= V h (bytes 16 n q (j + 3))
  *   family 2  first Gram-Schmidt inner products V^H W (bytes 16 n q (j + 1 + ceil(j / 8)))
+ *   family 3  5-point stencil y = A z of every Arnoldi step (eq. (lap1); bytes
+ *             32 n q: z read and y written once, coefficients from (h, k) in
+ *             registers; flops 40 n q)
  * Profiling inserts events between launches; leave it off for timing runs. */
 hh_status hh_profile(hh_ctx* c, int32_t enable);
 hh_status hh_profile_read(hh_ctx* c, int32_t family, int64_t* launches, double* total_ms, double* bytes,

@@ -1233,9 +1233,12 @@ hh_status arnoldi_step(hh_ctx* c, int q, int j, int maxit) {
   const c128* vj = w.Vb + j * vs;
   c128* zj = w.Zb + j * vs;
   HH_TRY(two_level(c, 0, q, vj, zj));
-  HH_CHECK(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, zj, nullptr, w.W, 0, s,
-                            w.state));
   const double vbytes = 16.0 * (double)n * q;
+  {
+    ProfScope ps(c, 3, 2.0 * vbytes, 40.0 * n * q);
+    HH_CHECK(launch_apply_box(c->d_ops, c->lv[0].d, c->lv[0].nbox, c->lv[0].max_n, q, zj, nullptr, w.W, 0, s,
+                              w.state));
+  }
   {
     ProfScope ps(c, 2, vbytes * (j + 1 + (j + 8) / 8), 8.0 * n * q * (j + 1));
     HH_CHECK(launch_multidot(j + 1, sg, w.Vb, vs, w.W, c->d_partial, w.h1, s, 1, w.state));
