@@ -239,8 +239,8 @@ def test_batch_invariance(hh):
 def test_columns_identical_across_coarse_kernel_paths(hh):
     """A column's bits do not depend on the batch width where the width picks
     another coarse restriction/prolongation kernel (vector FMA chains for up to
-    four right-hand sides, matrix cores for more): 20 columns solved together
-    and the first two alone."""
+    four right-hand sides, matrix cores for more): 20 columns solved together,
+    the first two alone and the first six alone."""
     from gpu_util import build_both, dev, host
 
     ctx, S = _case_2d(hh, 48, [(3, 3)], 12.0, 4, 6)
@@ -249,10 +249,11 @@ def test_columns_identical_across_coarse_kernel_paths(hh):
         f = W.smoothed_gaussian_rhs(48, 23, 20)
         u20 = dev(np.zeros_like(f))
         info20 = hh.hh_solve(ctx, dev(f), u20, rtol=1e-8, maxit=100)
-        u2 = dev(np.zeros_like(f[:2]))
-        info2 = hh.hh_solve(ctx, dev(f[:2]), u2, rtol=1e-8, maxit=100)
-        assert [i[0] for i in info2] == [i[0] for i in info20[:2]]
-        assert np.array_equal(host(u2), host(u20)[:2])
+        for w in (2, 6):
+            uw = dev(np.zeros_like(f[:w]))
+            infow = hh.hh_solve(ctx, dev(f[:w]), uw, rtol=1e-8, maxit=100)
+            assert [i[0] for i in infow] == [i[0] for i in info20[:w]]
+            assert np.array_equal(host(uw), host(u20)[:w])
     finally:
         hh.hh_destroy(ctx)
 
