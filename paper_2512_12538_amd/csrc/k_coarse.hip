@@ -478,22 +478,22 @@ __global__ void __launch_bounds__(TB) k_restrict_mfma(const BoxDev* __restrict__
 }
 
 // cvec[par][c][cidx + a] = sum over the child's chunks of part[g][a][c];
-// cbase[child] = its first chunk.  Work-group: 64 outputs (a, c) of one child
-// (lanes) x RS_SEG waves; wave k sums the chunks k, k + RS_SEG, ... in turn,
-// then wave 0 adds the RS_SEG partial sums in wave order.  The order depends on
-// the child's chunk count only (not on q): a box with thousands of chunks is
-// summed by 16 chains in parallel instead of one.
-constexpr int RS_SEG = 16;
-__global__ void __launch_bounds__(64 * RS_SEG) k_restrict_sum(const BoxDev* __restrict__ child,
-                                                              const ParentDev* __restrict__ pd,
-                                                              const int* __restrict__ cbase, int rpad, int q,
-                                                              int qpad, const c128* __restrict__ part,
-                                                              c128* __restrict__ cvec) {
+// cbase[child] = its first chunk.  Work-group: RS_OUT outputs (a, c) of one
+// child x RS_SEG chains; chain k sums the chunks k, k + RS_SEG, ... in turn,
+// then one thread per output adds the RS_SEG chain sums in chain order.  The
+// order depends on the child's chunk count only (not on q): a box with
+// thousands of chunks is summed by 64 chains in parallel instead of one.
+constexpr int RS_SEG = 64, RS_OUT = 16;
+__global__ void __launch_bounds__(RS_SEG * RS_OUT) k_restrict_sum(const BoxDev* __restrict__ child,
+                                                                  const ParentDev* __restrict__ pd,
+                                                                  const int* __restrict__ cbase, int rpad, int q,
+                                                                  int qpad, const c128* __restrict__ part,
+                                                                  c128* __restrict__ cvec) {
   const int box = blockIdx.y;
   const BoxDev B = child[box];
-  if (blockIdx.x * 64 >= B.r * q) return;  // the same for the whole work-group
-  const int lane = threadIdx.x & 63, sg = threadIdx.x >> 6;
-  const int idx = blockIdx.x * 64 + lane;
+  if (blockIdx.x * RS_OUT >= B.r * q) return;  // the same for the whole work-group
+  const int o = threadIdx.x % RS_OUT, sg = threadIdx.x / RS_OUT;
+  const int idx = blockIdx.x * RS_OUT + o;
   const int a = idx / q, c = idx - a * q;
   const bool live = a < B.r;
   const int nch = (B.n_own + RCH - 1) / RCH;
@@ -513,15 +513,14 @@ __global__ void __launch_bounds__(64 * RS_SEG) k_restrict_sum(const BoxDev* __re
     }
     for (; ch < nch; ch += RS_SEG) acc = cadd(acc, pb[ch * st]);
   }
-  __shared__ double2 red[RS_SEG][64];
-  red[sg][lane] = acc;
+  __shared__ double2 red[RS_SEG][RS_OUT];
+  red[sg][o] = acc;
   __syncthreads();
   if (sg == 0 && live) {
-    double2 s = red[0][lane];
-#pragma unroll
-    for (int k = 1; k < RS_SEG; ++k) s = cadd(s, red[k][lane]);
+    double2 sum = red[0][o];
+    for (int k = 1; k < RS_SEG; ++k) sum = cadd(sum, red[k][o]);
     const ParentDev D = pd[B.parent];
-    cvec[D.yoff * q + (long long)c * D.n_c + B.cidx + a] = s;
+    cvec[D.yoff * q + (long long)c * D.n_c + B.cidx + a] = sum;
   }
 }
 
@@ -929,8 +928,8 @@ hipError_t launch_coarse_restrict(const BoxDev* child, int nchild, const int2* c
   else
     hipLaunchKernelGGL(k_restrict_mfma<8>, grid, dim3(TB), 0, s, child, par, chunks, (int)nitems, ncg, q, C, t, part,
                        active);
-  hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + 63) / 64, nchild), dim3(64 * RS_SEG), 0, s, child, pd, cbase,
-                     16 * mt, q, ncg * 16, part, cvec);
+  hipLaunchKernelGGL(k_restrict_sum, dim3((rmax * q + RS_OUT - 1) / RS_OUT, nchild), dim3(RS_SEG * RS_OUT), 0, s,
+                     child, pd, cbase, 16 * mt, q, ncg * 16, part, cvec);
   return hipGetLastError();
 }
 
